@@ -1,0 +1,67 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake (a dropped term, a wrong sign or index, a wrong
+operand) into a copy of the oracle's FC source, loads the copy as a module and
+runs every pin on it; at least one pin must fail. Runs on the CPU only.
+"""
+import importlib.util
+import os
+import types
+
+import numpy as np
+import pytest
+
+from oracle_pins import ALL_PINS, TOL
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "fc.py")
+
+MUTATIONS = {
+    "dft_index": ("e = np.outer(k, k) % n", "e = np.outer(k, (k + 1) % n) % n"),
+    "tx_drop_sqrtI": ("yb = np.sqrt(ov.I) * phi * blocks[:, r]", "yb = phi * blocks[:, r]"),
+    "phi_sign": ("phi = unit_phase(r * c * ov.L_S, L)\n        yb", "phi = unit_phase(-r * c * ov.L_S, L)\n        yb"),
+    "xi_off_by_one": ("return (c - (-(-L // 2)) + np.arange(L)) % N", "return (c - (-(-L // 2)) + np.arange(L) + 1) % N"),
+    "tx_wrong_direction": ("return idft_matrix(N)[:, xi(L, N, c)] @ inner", "return dft_matrix(N)[:, xi(L, N, c)] @ inner / N"),
+    "drop_shift": ("inner = D[:, None] * (shift_matrix(L) @ dft_matrix(L))", "inner = D[:, None] * dft_matrix(L)"),
+    "weights_reversed": ("inner = D[:, None] * (shift_matrix(L) @ dft_matrix(L))", "inner = D[::-1, None] * (shift_matrix(L) @ dft_matrix(L))"),
+    "theta_dropped": ("theta = unit_phase(c * sigma[n], N)\n        wn", "theta = 1.0\n        wn"),
+    "theta_sign": ("theta = unit_phase(c * sigma[n], N)\n        wn", "theta = unit_phase(-c * sigma[n], N)\n        wn"),
+    "first_window_no_cp": ("a = [np.r_[np.zeros(S_L), np.ones(ov.L_S + lcp[n]), np.zeros(ov.L_T)],",
+                           "a = [np.r_[np.zeros(ov.L_L), np.ones(ov.L_S), np.zeros(ov.L_T)],"),
+    "windows_swapped": ("seg = z[r * L // 2:r * L // 2 + L] * a[r]", "seg = z[r * L // 2:r * L // 2 + L] * a[1 - r]"),
+    "sync_second_block_offset": ("wn[r * N // 2:r * N // 2 + N] += np.sqrt(ov.I)", "wn[r * N // 4:r * N // 4 + N] += np.sqrt(ov.I)"),
+    "sync_padding_wrong": ("S_L = ov.L_L - lcp[n]\n        z = np.r_", "S_L = ov.L_L - lcp[n] - 1\n        z = np.r_"),
+    "ola_window_dropped": ("    if ola:\n        segs = segs * a[:, None]", "    if False:\n        segs = segs * a[:, None]"),
+    "ols_keep_shifted": ("        if not ola:\n            yb = s * yb", "        if not ola:\n            yb = np.roll(s, 1) * yb"),
+    "rx_phase_not_conj": ("phi = np.conj(unit_phase(r * c * ov.L_S, L))\n        zr", "phi = unit_phase(r * c * ov.L_S, L)\n        zr"),
+    "rx_scale": ("zr = phi * z[:, r] / np.sqrt(ov.I)", "zr = phi * z[:, r] * np.sqrt(ov.I)"),
+    "rx_no_unshift": ("Pinv = shift_matrix(L).T", "Pinv = np.eye(L)"),
+    "rx_wrong_gather": ("return left @ dft_matrix(N)[xi(L, N, c), :]", "return left @ dft_matrix(N)[xi(L, N, -c), :]"),
+    "rx_sync_theta_missing": ("theta = np.conj(unit_phase(c * sigma[n], N))", "theta = 1.0"),
+    "concat_wrong_half": ("P[rows, L // 4 + np.arange(L // 2)] = 1.0", "P[rows, np.arange(L // 2)] = 1.0"),
+    "keep_cp_off_by_one": ("out.append(np.r_[z[0][S_L:3 * L // 4], z[1][L // 4:3 * L // 4]])",
+                           "out.append(np.r_[z[0][S_L + 1:3 * L // 4 + 1], z[1][L // 4:3 * L // 4]])"),
+}
+
+
+def load_mutant(name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation anchor for %s must match exactly once" % name
+    mod = types.ModuleType("oracle.fc_mutant_" + name)
+    mod.__package__ = "oracle"
+    mod.__file__ = SRC
+    exec(compile(src.replace(old, new), SRC + ":" + name, "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name):
+    mod = load_mutant(name, *MUTATIONS[name])
+    failed = []
+    for pin, fn in ALL_PINS.items():
+        try:
+            err = fn(mod)
+            if not np.isfinite(err) or err > TOL:
+                failed.append(pin)
+        except Exception:
+            failed.append(pin)
+    assert failed, "no pin caught mutation %s" % name

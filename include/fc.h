@@ -1,0 +1,227 @@
+/*
+ * fc.h - C ABI of the MI355X (gfx950) fast-convolution filtered CP-OFDM library.
+ *
+ * Implements the fast-convolution (FC) synthesis and analysis filter banks of
+ * Yli-Kaakinen et al., "Frequency-Domain Signal Processing for Spectrally-
+ * Enhanced CP-OFDM Waveforms in 5G New Radio" (arXiv 2008.00672):
+ *   - continuous FC with overlap-add (OLA) or overlap-save (OLS) blocks
+ *     (Sec. III-B, block operators F^(OLA), F^(OLS); Sec. IV, G^(OLA), G^(OLS));
+ *   - symbol-synchronised FC whose blocks align with every OFDM symbol and its
+ *     NR cyclic prefix, with CP truncation/extrapolation (Sec. III-C..III-E)
+ *     and the synchronised receiver with CP removal (Sec. IV).
+ *
+ * Conventions (all arguments are plain C types; no framework types cross this
+ * boundary):
+ *   - Samples are complex, stored interleaved (I, Q) in one of the I/O types
+ *     below. Arithmetic is always FP32 on the device; twiddles and block phases
+ *     are computed in FP64 on the host and rounded once to FP32.
+ *   - Naming: n_short is the paper's L_m (short transform, equal to the OFDM
+ *     IFFT length L_OFDM,m), n_long is the paper's N (long transform);
+ *     I = n_long / n_short is the interpolation factor.
+ *   - Every device pointer is owned by the caller and must stay valid until the
+ *     work queued on the given stream has completed. The plan owns its own
+ *     device tables (descriptors, twiddles, weights).
+ *   - Calls that take a stream are asynchronous on that stream (a hipStream_t
+ *     passed as void*; NULL means the default stream) and never synchronise the
+ *     host. A plan must not be used on two streams concurrently.
+ *   - Every function returns an fc_status and never aborts or throws across
+ *     the ABI. Argument and shape errors are detected on the host before any
+ *     device work is queued. HIP runtime failures surface as FC_E_DEVICE.
+ */
+#ifndef FC_H_
+#define FC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fc_status;
+enum {
+  FC_OK = 0,
+  FC_E_ARG = -1,          /* invalid argument value or NULL pointer          */
+  FC_E_SHAPE = -2,        /* inconsistent sizes (e.g. n_short does not divide n_long) */
+  FC_E_UNSUPPORTED = -3,  /* valid per the paper but not implemented here    */
+  FC_E_NOMEM = -4,        /* host or device allocation failed                */
+  FC_E_DEVICE = -5,       /* a HIP runtime call failed                       */
+  FC_E_STATE = -6         /* operation not valid for this plan               */
+};
+
+/* Processing model of a subband (Sec. III-B, III-C, IV). */
+enum {
+  FC_CONT_OLA = 0,   /* continuous, fixed overlap, overlap-add                 */
+  FC_CONT_OLS = 1,   /* continuous, fixed overlap, overlap-save                */
+  FC_SYNC_OLA = 2,   /* symbol-synchronised: OLA transmitter, CP-removing receiver */
+  FC_SYNC_OLS = 3    /* symbol-synchronised receiver only                      */
+};
+
+/* Storage type of the interleaved I/Q samples in device memory. */
+enum {
+  FC_IO_C64 = 0,     /* 2 x float32                                    */
+  FC_IO_F16 = 1,     /* 2 x IEEE binary16, round-to-nearest-even       */
+  FC_IO_BF16 = 2     /* 2 x bfloat16, round-to-nearest-even            */
+};
+
+/* Operation selector for layout queries. */
+enum {
+  FC_OP_TX = 0,      /* fc_tx_synthesize: low-rate CP-OFDM in, high-rate out            */
+  FC_OP_RX = 1,      /* fc_rx_analyze:    high-rate in, low-rate out                    */
+  FC_OP_ADJ = 2      /* fc_tx_adjoint:    high-rate in, low-rate CP-OFDM-shaped out     */
+};
+
+/*
+ * One subband (Sec. III-A/III-B; the paper's subband m).
+ *   scs_khz       subcarrier spacing 15 * 2^mu kHz (selects the NR CP rule)
+ *   first_symbol  index of the first symbol within its subframe (long-CP symbols
+ *                 are l = 0 and l = 7 * 2^mu of the subframe)
+ *   n_symbols     B_OFDM,m, number of OFDM symbols in the burst (>= 1)
+ *   n_active      L_act,m, active subcarriers K (even); passband kappa in [-K/2, K/2)
+ *   n_tb          transition-band bins per side (default weights, validation)
+ *   n_short       L_m = L_OFDM,m, power of two in [16, 4096]
+ *   n_long        N, power of two in [n_short, 4096]
+ *   center_bin    c_m, subband centre in long-transform bins (signed)
+ *   overlap_num/overlap_den  overlap factor lambda; synchronised modes need 1/2,
+ *                 continuous modes need 0 < lambda <= 1/2 with lambda*L_m even
+ *   mode          FC_CONT_OLA .. FC_SYNC_OLS
+ *   stream        index of the high-rate stream this subband is summed into /
+ *                 analysed from; streams are numbered 0..n_streams-1 densely
+ *   ncp_high      optional per-symbol high-rate CP lengths N_CP,n (n_symbols
+ *                 entries, read during fc_plan_create only); NULL selects the
+ *                 NR normal CP at rate n_long * SCS
+ */
+typedef struct fc_subband {
+  int32_t scs_khz;
+  int32_t first_symbol;
+  int32_t n_symbols;
+  int32_t n_active;
+  int32_t n_tb;
+  int32_t n_short;
+  int32_t n_long;
+  int32_t center_bin;
+  int32_t overlap_num;
+  int32_t overlap_den;
+  int32_t mode;
+  int32_t stream;
+  const int32_t* ncp_high;
+} fc_subband;
+
+typedef struct fc_plan fc_plan;
+
+/*
+ * Build a plan for n_sb subbands on device `device` with I/O type io_type.
+ * device = -1 builds a host-only plan: schedules, layouts and validation
+ * without device memory; compute calls on it return FC_E_STATE.
+ * Validates every subband (Sec. III-B/III-E constraints: n_short | n_long,
+ * K + 2 n_tb <= n_short, |c| + n_short/2 <= n_long/2, integer low-rate CP in
+ * continuous modes, truncated low-rate CP <= n_short/4 in synchronised modes,
+ * equal numerology, symbol count and CP schedule among subbands sharing a
+ * stream and n_long in one processing group). Initialises every subband's
+ * weights to a raised-cosine transition of n_tb bins. *plan receives the plan
+ * (or NULL on failure). Device memory for the plan's tables is allocated here.
+ */
+fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, int32_t device,
+                         fc_plan** plan);
+
+/* Release the plan and its device tables (after the queued work completed). */
+void fc_plan_destroy(fc_plan* plan);
+
+/* Number of subbands and streams of the plan. */
+fc_status fc_plan_counts(const fc_plan* plan, int32_t* n_sb, int32_t* n_streams);
+
+/*
+ * Buffer layout for operation `op`, in complex samples (not bytes):
+ *   lowrate_off[n_sb + 1]       subband m's low-rate samples are
+ *                               [lowrate_off[m], lowrate_off[m+1])
+ *   highrate_off[n_streams + 1] stream s's high-rate samples are
+ *                               [highrate_off[s], highrate_off[s+1])
+ * Low-rate layout: FC_OP_TX / FC_OP_ADJ and continuous FC_OP_RX use the
+ * concatenated CP-OFDM symbols (sum_n n_short + L_CP,n); synchronised FC_OP_RX
+ * returns n_symbols * n_short samples (CP removed, Sec. IV concatenation).
+ * Either pointer may be NULL.
+ */
+fc_status fc_plan_layout(const fc_plan* plan, int32_t op, int64_t* lowrate_off,
+                         int64_t* highrate_off);
+
+/*
+ * Per-symbol CP schedule of subband sb: ncp_high[n] = N_CP,n (high rate),
+ * ncp_low[n] = L_CP,n (low rate; floor(N_CP,n / I) in synchronised modes,
+ * Sec. III-E). Arrays of n_symbols entries; either may be NULL.
+ * offset (may be NULL) receives the position, in its stream, of sample 0 of
+ * this subband's local high-rate axis (groups on one stream are aligned so that
+ * their first CPs start together).
+ */
+fc_status fc_plan_symbols(const fc_plan* plan, int32_t sb, int32_t* ncp_high, int32_t* ncp_low,
+                          int64_t* offset);
+
+/*
+ * Frequency-domain window D_m of subband sb (Sec. III-B): n == n_short real
+ * weights in fftshifted order (index p is subcarrier kappa = p - n_short/2).
+ * Host pointer, copied; the device copy is updated on `stream` and the call
+ * returns once that copy has completed. Non-finite weights are rejected.
+ */
+fc_status fc_set_weights(fc_plan* plan, int32_t sb, const float* w_host, int32_t n, void* stream);
+
+/*
+ * Same as fc_set_weights with a device pointer w_dev (n == n_short floats):
+ * an asynchronous device-to-device copy on `stream`; the host is not
+ * synchronised and fc_get_weights reads the device copy.
+ */
+fc_status fc_set_weights_device(fc_plan* plan, int32_t sb, const float* w_dev, int32_t n, void* stream);
+
+/* Copy subband sb's current weights (n == n_short) to host memory w_host
+ * (waits for the device). */
+fc_status fc_get_weights(const fc_plan* plan, int32_t sb, float* w_host, int32_t n);
+
+/*
+ * FC synthesis filter bank (Sec. III-B, eq. for x_FC-F-OFDM; Sec. III-C..III-E):
+ * lowrate_in (device, FC_OP_TX layout) -> highrate_out (device, all streams).
+ * Every sample of every stream is written (zeros where no block contributes);
+ * subbands on one stream are summed. Supported modes: FC_CONT_OLA,
+ * FC_CONT_OLS, FC_SYNC_OLA.
+ */
+fc_status fc_tx_synthesize(fc_plan* plan, const void* lowrate_in, void* highrate_out, void* stream);
+
+/*
+ * FC analysis filter bank (Sec. IV): highrate_in (device) -> lowrate_out
+ * (device, FC_OP_RX layout). FC_CONT_OLS / FC_CONT_OLA use G^(OLS) / G^(OLA)
+ * with conj(phi) and scale 1/sqrt(I); synchronised modes use two blocks per
+ * symbol and return the CP-free symbols (Sec. IV concatenation).
+ */
+fc_status fc_rx_analyze(fc_plan* plan, const void* highrate_in, void* lowrate_out, void* stream);
+
+/*
+ * Exact adjoint of fc_tx_synthesize (used for gradients): highrate_in ->
+ * lowrate_out in the FC_OP_TX low-rate layout, so that
+ * <tx(x), y> = <x, adjoint(y)> for the plan's current weights.
+ */
+fc_status fc_tx_adjoint(fc_plan* plan, const void* highrate_in, void* lowrate_out, void* stream);
+
+/*
+ * Gradient of Re<g, tx(x)> with respect to every subband's weights:
+ * grad_w[k] for k in [0, sum_m n_short_m) (subbands concatenated in plan order,
+ * fftshifted order within a subband) is overwritten with
+ * sum over blocks of Re(conj(G_q) * phase * X_p) for the bin p of weight k,
+ * where X is the block's short FFT and G the long FFT of the matching block of
+ * grad_out. lowrate_in is the forward input, grad_out the high-rate gradient
+ * (both device, plan layouts); grad_w is a device float array.
+ */
+fc_status fc_tx_weight_grad(fc_plan* plan, const void* lowrate_in, const void* grad_out,
+                            float* grad_w, void* stream);
+
+/* Work decomposition of operation op: FC blocks, tasks (workgroup work
+ * items) and kernel launches per call. Either pointer may be NULL. */
+fc_status fc_plan_stats(const fc_plan* plan, int32_t op, int64_t* n_blocks, int64_t* n_tasks,
+                        int64_t* n_launches);
+
+/* Human-readable name of a status code (static string). */
+const char* fc_status_str(fc_status s);
+
+/* Library version string, e.g. "fc 0.1 gfx950". */
+const char* fc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FC_H_ */

@@ -1,0 +1,81 @@
+// Internal device descriptors shared by the host planner (fc_plan.cpp) and the
+// gfx950 kernels (fc_kernels.hip). Plain POD structs, 8-byte aligned.
+#pragma once
+#include <stdint.h>
+
+namespace fcx {
+
+// Largest transform handled in one workgroup: 256 threads x 16 complex values.
+constexpr int kThreads = 256;
+constexpr int kMaxPoints = 4096;
+constexpr int kTwiddleN = 4096;      // global twiddle table: exp(-j 2 pi k / 4096)
+
+enum IoType : int32_t { IO_C64 = 0, IO_F16 = 1, IO_BF16 = 2 };
+
+struct Cf {   // complex float with the same layout as HIP's float2
+  float x, y;
+};
+
+// One subband, shared by all operations.
+struct SbDesc {
+  int32_t L, logL;        // short transform length L_m
+  int32_t c;              // centre bin c_m (signed)
+  int32_t q0;             // (c_m - L_m/2) mod N: long bin of shifted index p = 0
+  int32_t w_off;          // offset of this subband's weights in the weight table
+  int32_t pad0;
+  int64_t lo_off;         // element offset of the subband's low-rate data for this op
+  int64_t lo_len;         // number of low-rate samples for this op
+};
+
+// One processing group: subbands sharing a stream, n_long and a block grid.
+struct GroupDesc {
+  int32_t N, logN;
+  int32_t n_sb, sb_first;    // subbands [sb_first, sb_first + n_sb) of the op's table
+  int32_t prune;             // TX: 1 when the long IFFT is evaluated as N/L short IFFTs
+  int32_t pad0;
+};
+
+// One FC block of a group.
+struct BlockDesc {
+  int64_t t0;                // absolute high-rate element index of block sample 0
+  int32_t hlo, hhi;          // TX: high-rate write window; RX: high-rate input window
+  int32_t bs;                // index of the block's first BlockSb entry
+  int32_t pad0;
+};
+
+// Per (block, subband).
+struct BlockSb {
+  int64_t x0;                // low-rate element index (absolute) of block sample 0
+  int32_t lo, hi;            // TX: valid input window; RX: low-rate keep window
+  Cf ph;                     // TX: sqrt(I)/N * phi_r theta_n; RX: conj(phi_r theta_n)/(sqrt(I) L)
+};
+
+// A unit of work: a run of consecutive blocks of one group.
+struct TaskDesc {
+  int32_t group;
+  int32_t blk_first, blk_count;
+  int32_t warm;              // 1: the first block only feeds the OLA carry
+  int64_t own_lo, own_hi;    // absolute high-rate (TX) / low-rate (RX) ownership
+  int64_t z0_lo, z0_hi;      // zero-fill ranges inside the owned range (TX assign)
+  int64_t z1_lo, z1_hi;
+  int32_t ola;               // 1: blocks overlap-add their outputs (carry in LDS)
+  int32_t accumulate;        // 1: out += value instead of out = value
+};
+
+// Launch arguments of one kernel phase.
+struct LaunchArgs {
+  const SbDesc* sb;
+  const GroupDesc* grp;
+  const BlockDesc* blk;
+  const BlockSb* bsb;
+  const TaskDesc* task;
+  int32_t n_task;
+  int32_t io;
+  const float* weights;
+  const Cf* twiddle;
+  unsigned int* counter;     // work counter (reset by the preceding reset kernel)
+  const void* in;
+  void* out;
+};
+
+}  // namespace fcx

@@ -1,0 +1,682 @@
+// Host planner and C ABI of the FC library.
+//
+// The planner turns subband descriptions (Sec. III-A/III-B problem statement)
+// into device tables: per-subband constants, processing groups (subbands that
+// share a stream, a long transform and a block grid), FC blocks with their
+// input/output windows and FP64-computed phases, and tasks (runs of blocks
+// processed by one workgroup). All schedule arithmetic is integer; phases are
+// evaluated in FP64 from integer-reduced arguments and rounded once to FP32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <new>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fc.h"
+#include "fc_internal.h"
+
+namespace fcx {
+hipError_t launch_tx(const LaunchArgs& a, int lmax, size_t lds, hipStream_t s);
+hipError_t launch_rx(const LaunchArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_zero(void* out, int64_t n, int io, hipStream_t s);
+hipError_t set_lds_limits(size_t bytes);
+}  // namespace fcx
+
+using namespace fcx;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) { int l = 0; while ((1 << l) < v) ++l; return l; }
+int64_t imod(int64_t a, int64_t m) { int64_t r = a % m; return r < 0 ? r + m : r; }
+
+// exp(j 2 pi num / den) with the integer argument reduced first, times scale.
+Cf unit_phase(int64_t num, int64_t den, double scale) {
+  const double ang = 2.0 * kPi * (double)imod(num, den) / (double)den;
+  return Cf{(float)(scale * std::cos(ang)), (float)(scale * std::sin(ang))};
+}
+
+// Host-side view of one subband.
+struct Sub {
+  fc_subband d;
+  int mu = 0, I = 1, L = 0, N = 0, logL = 0, logN = 0;
+  int LO = 0, LS = 0, LL = 0, LT = 0;
+  int64_t NO = 0, NS = 0, NL = 0, NT = 0;
+  bool sync = false, ola = false;
+  std::vector<int> ncp, lcp;   // high- and low-rate CP per symbol
+  std::vector<int64_t> pos;    // low-rate start of each symbol in the CP-OFDM stream
+  std::vector<int64_t> sig;    // sigma_n: high-rate start of each filtered symbol
+  int64_t n_in = 0;            // CP-OFDM stream length (low rate)
+  int64_t Q = 0;               // local high-rate span
+  int64_t first_cp = 0;        // local high-rate position of the first CP start
+  int group = -1;
+  int64_t offset = 0;          // position of local sample 0 in the stream
+  std::vector<float> w;        // weights (fftshifted)
+};
+
+struct Group {
+  int stream;
+  std::vector<int> subs;       // plan subband indices
+  int N;
+  bool sync, ola;
+  int64_t offset;              // within the stream
+  int64_t Q;
+  int rank;                    // order of the group within its stream
+  int R;                       // number of blocks
+};
+
+// Tables and launch phases of one operation.
+struct Op {
+  bool valid = false;
+  std::vector<int64_t> lo_off;            // n_sb + 1
+  std::vector<SbDesc> sb;
+  std::vector<GroupDesc> grp;
+  std::vector<BlockDesc> blk;
+  std::vector<BlockSb> bsb;
+  std::vector<TaskDesc> task;
+  struct Phase { int kind; int first, count; size_t lds; int lmax; int64_t zero_n; };
+  // kind: 0 = TX kernel, 1 = RX kernel, 2 = zero the output buffer
+  std::vector<Phase> phases;
+  // device copies
+  SbDesc* d_sb = nullptr; GroupDesc* d_grp = nullptr; BlockDesc* d_blk = nullptr;
+  BlockSb* d_bsb = nullptr; TaskDesc* d_task = nullptr;
+};
+
+}  // namespace
+
+struct fc_plan {
+  int device = 0, io = 0;
+  std::vector<Sub> subs;
+  std::vector<Group> groups;
+  int n_streams = 0;
+  std::vector<int64_t> hi_off;   // n_streams + 1
+  std::vector<int> w_off;        // per subband
+  int w_total = 0;
+  float* d_w = nullptr;
+  Cf* d_tw = nullptr;
+  Op op[3];
+};
+
+namespace {
+
+int nr_cp(int N, int mu, int l, int* out) {
+  if ((N * 144) % 2048 || ((int64_t)N * (1 << mu) * 16) % 2048) return FC_E_SHAPE;
+  int v = N * 144 / 2048;
+  if (l % (7 * (1 << mu)) == 0) v += (int)((int64_t)N * (1 << mu) * 16 / 2048);
+  *out = v;
+  return FC_OK;
+}
+
+std::vector<float> rc_default(int L, int K, int ntb) {
+  std::vector<float> D(L, 0.f);
+  const int h = L / 2;
+  for (int k = -K / 2; k < K / 2; ++k) D[h + k] = 1.f;
+  for (int i = 1; i <= ntb; ++i) {
+    const double w = 0.5 * (1.0 + std::cos(kPi * i / (ntb + 1)));
+    D[h + K / 2 - 1 + i] = (float)w;
+    D[h - K / 2 - i] = (float)w;
+  }
+  return D;
+}
+
+fc_status analyse(const fc_subband& d, Sub& s) {
+  s.d = d;
+  s.d.ncp_high = nullptr;
+  if (d.n_symbols < 1 || d.n_active < 0 || (d.n_active & 1) || d.n_tb < 0) return FC_E_ARG;
+  if (d.mode < FC_CONT_OLA || d.mode > FC_SYNC_OLS || d.stream < 0) return FC_E_ARG;
+  if (d.scs_khz <= 0 || d.scs_khz % 15) return FC_E_ARG;
+  int ratio = d.scs_khz / 15;
+  if (!is_pow2(ratio)) return FC_E_ARG;
+  s.mu = ilog2(ratio);
+  if (!is_pow2(d.n_short) || !is_pow2(d.n_long)) return FC_E_UNSUPPORTED;
+  if (d.n_short < 16 || d.n_long > kMaxPoints) return FC_E_UNSUPPORTED;
+  if (d.n_long < d.n_short) return FC_E_SHAPE;
+  if (d.n_active + 2 * d.n_tb > d.n_short) return FC_E_SHAPE;
+  if (std::abs((int64_t)d.center_bin) + d.n_short / 2 > d.n_long / 2) return FC_E_SHAPE;
+  if (d.overlap_den <= 0 || d.overlap_num <= 0 || 2 * d.overlap_num > d.overlap_den) return FC_E_UNSUPPORTED;
+  s.L = d.n_short; s.N = d.n_long; s.logL = ilog2(s.L); s.logN = ilog2(s.N); s.I = s.N / s.L;
+  s.sync = d.mode == FC_SYNC_OLA || d.mode == FC_SYNC_OLS;
+  s.ola = d.mode == FC_CONT_OLA || d.mode == FC_SYNC_OLA;
+  if (((int64_t)d.overlap_num * s.L) % d.overlap_den) return FC_E_SHAPE;
+  s.LO = (int)((int64_t)d.overlap_num * s.L / d.overlap_den);
+  if (s.LO & 1) return FC_E_SHAPE;         // N_L = I L_L needs an even split
+  if (s.sync && 2 * s.LO != s.L) return FC_E_UNSUPPORTED;
+  s.LS = s.L - s.LO; s.LL = (s.LO + 1) / 2; s.LT = s.LO / 2;
+  s.NO = (int64_t)s.I * s.LO; s.NS = s.N - s.NO; s.NL = (int64_t)s.I * s.LL; s.NT = (int64_t)s.I * s.LT;
+  // CP schedule (Sec. III-A rule or explicit list)
+  s.ncp.resize(d.n_symbols);
+  s.lcp.resize(d.n_symbols);
+  const int per_sf = 14 * (1 << s.mu);
+  for (int n = 0; n < d.n_symbols; ++n) {
+    int v;
+    if (d.ncp_high) {
+      v = d.ncp_high[n];
+      if (v < 0) return FC_E_ARG;
+    } else {
+      fc_status st = nr_cp(s.N, s.mu, (d.first_symbol + n) % per_sf, &v);
+      if (st) return st;
+    }
+    s.ncp[n] = v;
+    if (!s.sync && v % s.I) return FC_E_SHAPE;      // continuous: integer low-rate CP
+    s.lcp[n] = v / s.I;                             // floor (Sec. III-E)
+    if (s.sync && (s.lcp[n] > s.LL || 2 * (int64_t)v >= s.N)) return FC_E_SHAPE;
+  }
+  s.pos.resize(d.n_symbols);
+  int64_t p = 0;
+  for (int n = 0; n < d.n_symbols; ++n) { s.pos[n] = p; p += s.L + s.lcp[n]; }
+  s.n_in = p;
+  // sigma_n = n N_OFDM + sum_{q=1..n} N_CP,q (Sec. III-D), N_OFDM = I L_OFDM = N
+  s.sig.resize(d.n_symbols);
+  int64_t acc = 0;
+  for (int n = 0; n < d.n_symbols; ++n) {
+    if (n > 0) acc += s.ncp[n];
+    s.sig[n] = (int64_t)n * s.N + acc;
+  }
+  if (s.sync) {
+    s.Q = s.NL + s.NT + (int64_t)d.n_symbols * s.N;
+    for (int n = 1; n < d.n_symbols; ++n) s.Q += s.ncp[n];
+    s.first_cp = s.NL - s.ncp[0];
+  } else {
+    const int64_t R = (s.n_in + s.LT + s.LS - 1) / s.LS;
+    s.Q = (R - 1) * s.NS + s.N;
+    s.first_cp = s.NO;
+  }
+  s.w = rc_default(s.L, d.n_active, d.n_tb);
+  return FC_OK;
+}
+
+int64_t sigma(const Sub& s, int n) { return s.sig[n]; }
+
+template <class T>
+fc_status upload(const std::vector<T>& h, T** d) {
+  *d = nullptr;
+  if (h.empty()) return FC_OK;
+  if (hipMalloc((void**)d, h.size() * sizeof(T)) != hipSuccess) { *d = nullptr; return FC_E_NOMEM; }
+  if (hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return FC_E_DEVICE;
+  return FC_OK;
+}
+
+// Block windows of one subband for one operation.
+// kind: 0 TX, 1 RX (paper's receiver of the mode), 2 adjoint of TX.
+struct Win { int64_t x0; int lo, hi; };
+
+Win clip_valid(const Sub& s, int64_t xrel, int lo, int hi, int64_t len) {
+  // keep local positions i in [lo, hi) with 0 <= xrel + i < len
+  int64_t a = std::max<int64_t>(lo, -xrel), b = std::min<int64_t>(hi, len - xrel);
+  if (b < a) b = a;
+  return Win{xrel, (int)a, (int)b};
+}
+
+void build_op(fc_plan* P, int kind) {
+  Op& op = P->op[kind];
+  op = Op();
+  const int nsb = (int)P->subs.size();
+  // validity: TX needs CONT_* or SYNC_OLA; ADJ likewise; RX any
+  for (const Sub& s : P->subs) {
+    if (kind != 1 && s.d.mode == FC_SYNC_OLS) return;
+  }
+  op.valid = true;
+  // low-rate layout
+  op.lo_off.assign(nsb + 1, 0);
+  for (int m = 0; m < nsb; ++m) {
+    const Sub& s = P->subs[m];
+    const int64_t len = (kind == 1 && s.sync) ? (int64_t)s.d.n_symbols * s.L : s.n_in;
+    op.lo_off[m + 1] = op.lo_off[m] + len;
+  }
+  // subband table in group order
+  std::vector<int> sb_index(nsb, -1);
+  for (size_t g = 0; g < P->groups.size(); ++g) {
+    const Group& G = P->groups[g];
+    GroupDesc gd{};
+    gd.N = G.N; gd.logN = ilog2(G.N);
+    gd.n_sb = (int)G.subs.size(); gd.sb_first = (int)op.sb.size();
+    const Sub& s0 = P->subs[G.subs[0]];
+    gd.prune = (kind == 0 && G.subs.size() == 1 && s0.I >= 2 && s0.L >= 16) ? 1 : 0;
+    op.grp.push_back(gd);
+    for (int m : G.subs) {
+      const Sub& s = P->subs[m];
+      SbDesc d{};
+      d.L = s.L; d.logL = s.logL; d.c = s.d.center_bin;
+      d.q0 = (int)imod((int64_t)s.d.center_bin - s.L / 2, s.N);
+      d.w_off = P->w_off[m];
+      d.lo_off = op.lo_off[m]; d.lo_len = op.lo_off[m + 1] - op.lo_off[m];
+      sb_index[m] = (int)op.sb.size();
+      op.sb.push_back(d);
+    }
+  }
+  // blocks and tasks
+  struct PhaseTasks { std::vector<TaskDesc> t; int lmax = 0; size_t lds = 0; };
+  std::map<int, PhaseTasks> tx_phase;        // TX: by group rank within the stream
+  PhaseTasks rx_all, rx_even, rx_odd;
+  bool any_acc_tx = false, any_ola_rx = false;
+  for (size_t g = 0; g < P->groups.size(); ++g) {
+    const Group& G = P->groups[g];
+    const Sub& s0 = P->subs[G.subs[0]];
+    const int N = G.N;
+    const int64_t base = P->hi_off[G.stream] + G.offset;
+    const int first_blk = (int)op.blk.size();
+    int lmax = 0;
+    for (int m : G.subs) lmax = std::max(lmax, P->subs[m].L);
+    // --- blocks ---
+    const int nblk = G.sync ? 2 * s0.d.n_symbols : G.R;
+    for (int b = 0; b < nblk; ++b) {
+      BlockDesc bd{};
+      int64_t t_local;
+      const int n = b >> 1, r = G.sync ? (b & 1) : b;
+      if (G.sync) t_local = sigma(s0, n) + (int64_t)(b & 1) * (N / 2);
+      else t_local = (int64_t)b * s0.NS;
+      bd.t0 = base + t_local;
+      // high-rate window
+      if (kind == 0) {
+        if (!G.sync && !G.ola) { bd.hlo = (int)s0.NL; bd.hhi = (int)(s0.NL + s0.NS); }
+        else { bd.hlo = 0; bd.hhi = N; }
+      } else {
+        // RX of CONT_OLA (G^(OLA)) and ADJ of CONT_OLS window the high-rate input
+        const bool win = !G.sync && ((kind == 1 && G.ola) || (kind == 2 && !G.ola));
+        if (win) { bd.hlo = (int)s0.NL; bd.hhi = (int)(s0.NL + s0.NS); }
+        else { bd.hlo = 0; bd.hhi = N; }
+      }
+      bd.bs = (int)op.bsb.size();
+      op.blk.push_back(bd);
+      for (int m : G.subs) {
+        const Sub& s = P->subs[m];
+        const int L = s.L;
+        BlockSb z{};
+        Win w{};
+        int64_t phase_num;       // exponent of exp(j 2 pi phase_num / N)
+        if (G.sync) {
+          const int S_L = s.LL - s.lcp[n];
+          phase_num = (int64_t)r * s.d.center_bin * (N / 2) + (int64_t)s.d.center_bin * sigma(s, n);
+          if (kind == 1) {
+            // Sec. IV concatenation: keep [L/4, 3L/4) of both blocks, CP removed
+            const int64_t xrel = (int64_t)n * L + (int64_t)r * (L / 2) - L / 4;
+            w = Win{xrel, L / 4, 3 * L / 4};
+          } else {
+            const int64_t xrel = s.pos[n] + (int64_t)r * (L / 2) - S_L;
+            w = (r == 0) ? Win{xrel, S_L, 3 * L / 4} : Win{xrel, L / 4, 3 * L / 4};
+          }
+        } else {
+          phase_num = (int64_t)r * s.d.center_bin * s.LS * s.I;   // r c L_S / L in units of 1/N
+          const int64_t xrel = (int64_t)r * s.LS - s.LO;
+          bool low_window;      // TX input window a / RX keep window a, else full block
+          if (kind == 0) low_window = G.ola;
+          else if (kind == 1) low_window = !G.ola;           // G^(OLS) keeps [L_L, L_L + L_S)
+          else low_window = G.ola;                           // adjoint of TX-OLA: keep a
+          w = low_window ? clip_valid(s, xrel, s.LL, s.LL + s.LS, s.n_in)
+                         : clip_valid(s, xrel, 0, L, s.n_in);
+        }
+        z.x0 = op.lo_off[m] + w.x0;
+        z.lo = w.lo; z.hi = w.hi;
+        if (kind == 0) z.ph = unit_phase(phase_num, N, std::sqrt((double)s.I) / N);
+        else z.ph = unit_phase(-phase_num, N, 1.0 / (std::sqrt((double)s.I) * L));
+        op.bsb.push_back(z);
+      }
+    }
+    const int64_t span_lo = base, span_hi = base + G.Q;
+    if (kind == 0) {
+      // --- TX runs ---
+      const bool acc = P->groups.size() > 1 &&
+          std::count_if(P->groups.begin(), P->groups.end(), [&](const Group& o) { return o.stream == G.stream; }) > 1;
+      any_acc_tx |= acc;
+      const bool ola = G.sync || G.ola;
+      int64_t total_blocks = 0;
+      for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
+      int K = (int)std::max<int64_t>(8, std::min<int64_t>(64, total_blocks / 2048));
+      if (G.sync) K += K & 1;                           // whole symbols per run
+      for (int b0 = 0; b0 < nblk; b0 += K) {
+        const int b1 = std::min(nblk, b0 + K);
+        TaskDesc t{};
+        t.group = (int)g;
+        t.ola = ola ? 1 : 0;
+        t.accumulate = acc ? 1 : 0;
+        t.warm = (ola && b0 > 0) ? 1 : 0;
+        t.blk_first = first_blk + b0 - t.warm;
+        t.blk_count = b1 - b0 + t.warm;
+        const BlockDesc& B0 = op.blk[first_blk + b0];
+        const BlockDesc& Bl = op.blk[first_blk + b1 - 1];
+        if (ola) {
+          t.own_lo = (b0 == 0) ? span_lo : B0.t0;
+          t.own_hi = (b1 == nblk) ? span_hi : op.blk[first_blk + b1].t0;
+        } else {
+          t.own_lo = (b0 == 0) ? span_lo : B0.t0 + B0.hlo;
+          t.own_hi = (b1 == nblk) ? span_hi : Bl.t0 + Bl.hhi;
+          if (!acc) {
+            if (b0 == 0) { t.z0_lo = span_lo; t.z0_hi = B0.t0 + B0.hlo; }
+            if (b1 == nblk) { t.z1_lo = Bl.t0 + Bl.hhi; t.z1_hi = span_hi; }
+          }
+        }
+        PhaseTasks& ph = tx_phase[G.rank];
+        ph.t.push_back(t);
+        ph.lmax = std::max(ph.lmax, lmax);
+        const GroupDesc& gd = op.grp[g];
+        const size_t lds = gd.prune ? (size_t)(N + N / 2) * 8 : (size_t)(N + lmax + N / 2) * 8;
+        ph.lds = std::max(ph.lds, lds);
+      }
+    } else {
+      // --- RX tasks: one block each ---
+      const bool acc = !G.sync && ((kind == 1 && G.ola) || (kind == 2 && !G.ola));
+      any_ola_rx |= acc;
+      for (int b = 0; b < nblk; ++b) {
+        TaskDesc t{};
+        t.group = (int)g; t.blk_first = first_blk + b; t.blk_count = 1;
+        t.accumulate = acc ? 1 : 0;
+        PhaseTasks& ph = acc ? ((b & 1) ? rx_odd : rx_even) : rx_all;
+        ph.t.push_back(t);
+        ph.lmax = std::max(ph.lmax, lmax);
+        ph.lds = std::max(ph.lds, (size_t)(N + lmax) * 8);
+      }
+    }
+  }
+  auto emit = [&](int kindk, PhaseTasks& ph) {
+    if (ph.t.empty()) return;
+    // heavier tasks first: the dispatcher hands workgroups out in index order
+    std::stable_sort(ph.t.begin(), ph.t.end(), [&](const TaskDesc& a, const TaskDesc& b) {
+      auto cost = [&](const TaskDesc& t) { return (int64_t)op.grp[t.group].N * t.blk_count; };
+      return cost(a) > cost(b);
+    });
+    Op::Phase p{kindk, (int)op.task.size(), (int)ph.t.size(), ph.lds, ph.lmax, 0};
+    op.task.insert(op.task.end(), ph.t.begin(), ph.t.end());
+    op.phases.push_back(p);
+  };
+  if (kind == 0) {
+    if (any_acc_tx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, P->hi_off.back()});
+    for (auto& kv : tx_phase) emit(0, kv.second);
+  } else {
+    if (any_ola_rx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, op.lo_off.back()});
+    // RX tasks keep block order (neighbouring blocks share input in L2)
+    if (!rx_all.t.empty()) {
+      Op::Phase p{1, (int)op.task.size(), (int)rx_all.t.size(), rx_all.lds, rx_all.lmax, 0};
+      op.task.insert(op.task.end(), rx_all.t.begin(), rx_all.t.end());
+      op.phases.push_back(p);
+    }
+    for (PhaseTasks* ph : {&rx_even, &rx_odd}) {
+      if (ph->t.empty()) continue;
+      Op::Phase p{1, (int)op.task.size(), (int)ph->t.size(), ph->lds, ph->lmax, 0};
+      op.task.insert(op.task.end(), ph->t.begin(), ph->t.end());
+      op.phases.push_back(p);
+    }
+  }
+}
+
+fc_status upload_op(Op& op) {
+  if (!op.valid) return FC_OK;
+  fc_status s;
+  if ((s = upload(op.sb, &op.d_sb))) return s;
+  if ((s = upload(op.grp, &op.d_grp))) return s;
+  if ((s = upload(op.blk, &op.d_blk))) return s;
+  if ((s = upload(op.bsb, &op.d_bsb))) return s;
+  if ((s = upload(op.task, &op.d_task))) return s;
+  return FC_OK;
+}
+
+void free_op(Op& op) {
+  hipFree(op.d_sb); hipFree(op.d_grp); hipFree(op.d_blk); hipFree(op.d_bsb); hipFree(op.d_task);
+  op.d_sb = nullptr; op.d_grp = nullptr; op.d_blk = nullptr; op.d_bsb = nullptr; op.d_task = nullptr;
+}
+
+fc_status run_op(fc_plan* P, int kind, const void* in, void* out, hipStream_t st) {
+  Op& op = P->op[kind];
+  if (!op.valid || P->device < 0) return FC_E_STATE;
+  if (!in || !out) return FC_E_ARG;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
+  if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
+  fc_status result = FC_OK;
+  for (const Op::Phase& ph : op.phases) {
+    hipError_t e = hipSuccess;
+    if (ph.kind == 2) {
+      e = launch_zero(out, ph.zero_n, P->io, st);
+    } else {
+      LaunchArgs a{};
+      a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
+      a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
+      a.weights = P->d_w; a.twiddle = P->d_tw; a.counter = nullptr;
+      a.in = in; a.out = out;
+      e = ph.kind == 0 ? launch_tx(a, ph.lmax, ph.lds, st) : launch_rx(a, ph.lds, st);
+    }
+    if (e != hipSuccess) { result = FC_E_DEVICE; break; }
+  }
+  if (cur != P->device) hipSetDevice(cur);
+  return result;
+}
+
+}  // namespace
+
+// ===================================================================== ABI ==
+extern "C" {
+
+const char* fc_status_str(fc_status s) {
+  switch (s) {
+    case FC_OK: return "ok";
+    case FC_E_ARG: return "invalid argument";
+    case FC_E_SHAPE: return "inconsistent sizes";
+    case FC_E_UNSUPPORTED: return "unsupported configuration";
+    case FC_E_NOMEM: return "out of memory";
+    case FC_E_DEVICE: return "HIP runtime error";
+    case FC_E_STATE: return "operation not valid for this plan";
+    default: return "unknown status";
+  }
+}
+
+const char* fc_version(void) { return "fc 0.1 gfx950"; }
+
+fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, int32_t device, fc_plan** plan) {
+  if (!plan) return FC_E_ARG;
+  *plan = nullptr;
+  if (!sb || n_sb <= 0 || io_type < FC_IO_C64 || io_type > FC_IO_BF16 || device < -1) return FC_E_ARG;
+  fc_plan* P = new (std::nothrow) fc_plan();
+  if (!P) return FC_E_NOMEM;
+  P->device = device;
+  P->io = io_type;
+  P->subs.resize(n_sb);
+  int max_stream = -1;
+  for (int m = 0; m < n_sb; ++m) {
+    fc_status s = analyse(sb[m], P->subs[m]);
+    if (s) { delete P; return s; }
+    max_stream = std::max(max_stream, sb[m].stream);
+  }
+  P->n_streams = max_stream + 1;
+  std::vector<int> used(P->n_streams, 0);
+  for (int m = 0; m < n_sb; ++m) used[sb[m].stream] = 1;
+  for (int u : used) if (!u) { delete P; return FC_E_ARG; }
+  // processing groups: same stream, long transform, model and CP schedule
+  std::map<std::tuple<int, int, int, int, int, std::vector<int>>, int> key2g;
+  for (int m = 0; m < n_sb; ++m) {
+    Sub& s = P->subs[m];
+    auto key = std::make_tuple(s.d.stream, s.N, s.d.mode, s.d.overlap_num * 4096 / s.d.overlap_den,
+                               s.d.n_symbols, s.ncp);
+    auto it = key2g.find(key);
+    if (it == key2g.end()) {
+      Group g{};
+      g.stream = s.d.stream; g.N = s.N; g.sync = s.sync; g.ola = s.ola;
+      g.Q = s.Q;
+      g.R = s.sync ? 2 * s.d.n_symbols : (int)((s.n_in + s.LT + s.LS - 1) / s.LS);
+      key2g[key] = (int)P->groups.size();
+      P->groups.push_back(g);
+      it = key2g.find(key);
+    }
+    Group& g = P->groups[it->second];
+    if (g.Q != s.Q) { delete P; return FC_E_SHAPE; }
+    g.subs.push_back(m);
+    s.group = it->second;
+  }
+  // align the groups of each stream on their first CP start; stream lengths
+  std::vector<int64_t> len(P->n_streams, 0), tmax(P->n_streams, INT64_MIN);
+  std::vector<int> rank(P->n_streams, 0);
+  for (Group& g : P->groups) {
+    const Sub& s = P->subs[g.subs[0]];
+    tmax[g.stream] = std::max(tmax[g.stream], s.first_cp);
+    g.rank = rank[g.stream]++;
+  }
+  for (Group& g : P->groups) {
+    const Sub& s = P->subs[g.subs[0]];
+    g.offset = tmax[g.stream] - s.first_cp;
+    len[g.stream] = std::max(len[g.stream], g.offset + g.Q);
+    for (int m : g.subs) P->subs[m].offset = g.offset;
+  }
+  P->hi_off.assign(P->n_streams + 1, 0);
+  for (int k = 0; k < P->n_streams; ++k) P->hi_off[k + 1] = P->hi_off[k] + len[k];
+  // weights
+  P->w_off.resize(n_sb);
+  for (int m = 0; m < n_sb; ++m) { P->w_off[m] = P->w_total; P->w_total += P->subs[m].L; }
+  // host tables
+  for (int k = 0; k < 3; ++k) build_op(P, k);
+  if (device < 0) {        // host-only plan: schedules and layouts, no device state
+    *plan = P;
+    return FC_OK;
+  }
+  // device state
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) { delete P; return FC_E_DEVICE; }
+  if (hipSetDevice(device) != hipSuccess) { delete P; return FC_E_DEVICE; }
+  fc_status st = FC_OK;
+  std::vector<Cf> tw(kTwiddleN);
+  for (int k = 0; k < kTwiddleN; ++k) {
+    const double a = 2.0 * kPi * k / kTwiddleN;
+    tw[k] = Cf{(float)std::cos(a), (float)-std::sin(a)};
+  }
+  std::vector<float> w(P->w_total);
+  for (int m = 0; m < n_sb; ++m) std::copy(P->subs[m].w.begin(), P->subs[m].w.end(), w.begin() + P->w_off[m]);
+  if (!st) st = upload(tw, &P->d_tw);
+  if (!st) st = upload(w, &P->d_w);
+  for (int k = 0; k < 3 && !st; ++k) st = upload_op(P->op[k]);
+  size_t lds_max = 0;
+  for (int k = 0; k < 3; ++k)
+    for (auto& ph : P->op[k].phases) lds_max = std::max(lds_max, ph.lds);
+  if (!st && lds_max > 65536 && set_lds_limits(lds_max) != hipSuccess) st = FC_E_UNSUPPORTED;
+  hipSetDevice(cur);
+  if (st) { fc_plan_destroy(P); return st; }
+  *plan = P;
+  return FC_OK;
+}
+
+void fc_plan_destroy(fc_plan* P) {
+  if (!P) return;
+  if (P->device < 0) { delete P; return; }
+  int cur = -1;
+  hipGetDevice(&cur);
+  hipSetDevice(P->device);
+  for (int k = 0; k < 3; ++k) free_op(P->op[k]);
+  hipFree(P->d_w);
+  hipFree(P->d_tw);
+  if (cur >= 0) hipSetDevice(cur);
+  delete P;
+}
+
+fc_status fc_plan_counts(const fc_plan* P, int32_t* n_sb, int32_t* n_streams) {
+  if (!P) return FC_E_ARG;
+  if (n_sb) *n_sb = (int32_t)P->subs.size();
+  if (n_streams) *n_streams = P->n_streams;
+  return FC_OK;
+}
+
+fc_status fc_plan_layout(const fc_plan* P, int32_t op, int64_t* lowrate_off, int64_t* highrate_off) {
+  if (!P || op < FC_OP_TX || op > FC_OP_ADJ) return FC_E_ARG;
+  const Op& o = P->op[op];
+  if (!o.valid) return FC_E_STATE;
+  if (lowrate_off) std::copy(o.lo_off.begin(), o.lo_off.end(), lowrate_off);
+  if (highrate_off) std::copy(P->hi_off.begin(), P->hi_off.end(), highrate_off);
+  return FC_OK;
+}
+
+fc_status fc_plan_symbols(const fc_plan* P, int32_t sb, int32_t* ncp_high, int32_t* ncp_low, int64_t* offset) {
+  if (!P || sb < 0 || sb >= (int)P->subs.size()) return FC_E_ARG;
+  const Sub& s = P->subs[sb];
+  if (ncp_high) std::copy(s.ncp.begin(), s.ncp.end(), ncp_high);
+  if (ncp_low) std::copy(s.lcp.begin(), s.lcp.end(), ncp_low);
+  if (offset) *offset = s.offset;
+  return FC_OK;
+}
+
+fc_status fc_set_weights(fc_plan* P, int32_t sb, const float* w_host, int32_t n, void* stream) {
+  if (!P || !w_host || sb < 0 || sb >= (int)P->subs.size()) return FC_E_ARG;
+  Sub& s = P->subs[sb];
+  if (n != s.L) return FC_E_SHAPE;
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(w_host[i])) return FC_E_ARG;
+  std::copy(w_host, w_host + n, s.w.begin());
+  if (P->device < 0) return FC_OK;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
+  if (cur != P->device) hipSetDevice(P->device);
+  hipError_t e = hipMemcpyAsync(P->d_w + P->w_off[sb], s.w.data(), n * sizeof(float), hipMemcpyHostToDevice,
+                                (hipStream_t)stream);
+  // the plan's host copy is rewritten by the next call: wait for this copy
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (cur != P->device) hipSetDevice(cur);
+  return e == hipSuccess ? FC_OK : FC_E_DEVICE;
+}
+
+fc_status fc_set_weights_device(fc_plan* P, int32_t sb, const float* w_dev, int32_t n, void* stream) {
+  if (!P || !w_dev || sb < 0 || sb >= (int)P->subs.size()) return FC_E_ARG;
+  if (P->device < 0) return FC_E_STATE;
+  const Sub& s = P->subs[sb];
+  if (n != s.L) return FC_E_SHAPE;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
+  if (cur != P->device) hipSetDevice(P->device);
+  hipError_t e = hipMemcpyAsync(P->d_w + P->w_off[sb], w_dev, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream);
+  if (cur != P->device) hipSetDevice(cur);
+  return e == hipSuccess ? FC_OK : FC_E_DEVICE;
+}
+
+fc_status fc_get_weights(const fc_plan* P, int32_t sb, float* w_host, int32_t n) {
+  if (!P || !w_host || sb < 0 || sb >= (int)P->subs.size()) return FC_E_ARG;
+  const Sub& s = P->subs[sb];
+  if (n != s.L) return FC_E_SHAPE;
+  if (P->device < 0) {
+    std::copy(s.w.begin(), s.w.end(), w_host);
+    return FC_OK;
+  }
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
+  if (cur != P->device) hipSetDevice(P->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(w_host, P->d_w + P->w_off[sb], n * sizeof(float), hipMemcpyDeviceToHost);
+  if (cur != P->device) hipSetDevice(cur);
+  return e == hipSuccess ? FC_OK : FC_E_DEVICE;
+}
+
+fc_status fc_plan_stats(const fc_plan* P, int32_t op, int64_t* n_blocks, int64_t* n_tasks, int64_t* n_launches) {
+  if (!P || op < FC_OP_TX || op > FC_OP_ADJ) return FC_E_ARG;
+  const Op& o = P->op[op];
+  if (!o.valid) return FC_E_STATE;
+  if (n_blocks) *n_blocks = (int64_t)o.blk.size();
+  if (n_tasks) *n_tasks = (int64_t)o.task.size();
+  if (n_launches) *n_launches = (int64_t)o.phases.size();
+  return FC_OK;
+}
+
+fc_status fc_tx_synthesize(fc_plan* P, const void* in, void* out, void* stream) {
+  if (!P) return FC_E_ARG;
+  return run_op(P, FC_OP_TX, in, out, (hipStream_t)stream);
+}
+
+fc_status fc_rx_analyze(fc_plan* P, const void* in, void* out, void* stream) {
+  if (!P) return FC_E_ARG;
+  return run_op(P, FC_OP_RX, in, out, (hipStream_t)stream);
+}
+
+fc_status fc_tx_adjoint(fc_plan* P, const void* in, void* out, void* stream) {
+  if (!P) return FC_E_ARG;
+  return run_op(P, FC_OP_ADJ, in, out, (hipStream_t)stream);
+}
+
+fc_status fc_tx_weight_grad(fc_plan* P, const void* lowrate_in, const void* grad_out, float* grad_w,
+                            void* stream) {
+  (void)lowrate_in; (void)grad_out; (void)grad_w; (void)stream;
+  if (!P) return FC_E_ARG;
+  return FC_E_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+"""Test helpers: seeded inputs and oracle references for whole plans.
+
+The oracle side computes stream alignment, CP schedules and outputs from
+``oracle`` only; nothing here reads anything from the HIP path except the
+outputs being checked.
+"""
+from fractions import Fraction
+
+import numpy as np
+
+import fcsynth
+from oracle import fc as ofc
+from oracle import lin as olin
+from oracle import numerology as nu
+from oracle import weights as ow
+
+
+def sub_params(s):
+    mu = nu.mu_of_scs(s["scs_khz"])
+    L, N = s["n_short"], s["n_long"]
+    lam = Fraction(*s.get("overlap", (1, 2)))
+    ncp = s.get("ncp_high") or nu.nr_cp_list(N, mu, s.get("first_symbol", 0), s["n_symbols"])
+    sync = s["mode"].startswith("sync")
+    lcp = nu.lowrate_cp(ncp, N // L, exact=not sync)
+    ov = nu.Overlap(L, N, lam)
+    n_in = sum(L + c for c in lcp)
+    Q = nu.sync_output_len(ncp, ov) if sync else nu.cont_output_len(n_in, ov)
+    return dict(L=L, N=N, lam=lam, ncp=list(ncp), lcp=lcp, ov=ov, sync=sync, n_in=n_in, Q=Q,
+                ola=s["mode"] in ("cont_ola", "sync_ola"), c=s["center_bin"], K=s["n_active"])
+
+
+def stream_offsets(subbands):
+    """Local-axis offset of every subband in its stream (first CPs aligned)
+    and the stream lengths."""
+    P = [sub_params(s) for s in subbands]
+    T = [nu.first_cp_start(p["sync"], p["ov"], p["ncp"][0]) for p in P]
+    n_st = max(s["stream"] for s in subbands) + 1
+    tmax = [max(T[i] for i, s in enumerate(subbands) if s["stream"] == k) for k in range(n_st)]
+    off = [tmax[s["stream"]] - T[i] for i, s in enumerate(subbands)]
+    lens = [max(off[i] + P[i]["Q"] for i, s in enumerate(subbands) if s["stream"] == k) for k in range(n_st)]
+    return off, lens, P
+
+
+def make_inputs(subbands, qam_order, seed, weights="rc"):
+    """Low-rate CP-OFDM input per subband (complex128) and weights per subband."""
+    rng = np.random.default_rng(seed)
+    xs, Ds, grids = [], [], []
+    for s in subbands:
+        p = sub_params(s)
+        g = fcsynth.qam_grid(rng, qam_order, s["n_symbols"], p["K"])
+        grids.append(g)
+        xs.append(fcsynth.cp_ofdm(g, p["L"], p["lcp"]))
+        if weights == "rc":
+            Ds.append(ow.rc_weights(p["L"], p["K"], s["n_tb"]))
+        else:
+            Ds.append(rng.uniform(-1.0, 1.0, p["L"]))
+    return xs, Ds, grids
+
+
+def oracle_tx(subbands, xs, Ds, reference="fc"):
+    off, lens, P = stream_offsets(subbands)
+    streams = [np.zeros(n, dtype=complex) for n in lens]
+    for i, s in enumerate(subbands):
+        p = P[i]
+        if reference == "fc":
+            if p["sync"]:
+                y = ofc.tx_sync(xs[i], p["L"], p["N"], p["c"], Ds[i], p["ncp"])
+            else:
+                y = ofc.tx_cont(xs[i], p["L"], p["N"], p["c"], Ds[i], lam=p["lam"], ola=p["ola"])
+        else:
+            if p["sync"]:
+                y = olin.tx_sync_lin(xs[i], p["L"], p["N"], p["c"], Ds[i], p["ncp"])
+            else:
+                y = olin.tx_cont_lin(xs[i], p["L"], p["N"], p["c"], Ds[i], lam=p["lam"])
+        streams[s["stream"]][off[i]:off[i] + len(y)] += y
+    return streams
+
+
+def oracle_rx(subbands, streams, Ds):
+    off, lens, P = stream_offsets(subbands)
+    outs = []
+    for i, s in enumerate(subbands):
+        p = P[i]
+        seg = streams[s["stream"]][off[i]:off[i] + p["Q"]]
+        if p["sync"]:
+            outs.append(ofc.rx_sync(seg, p["L"], p["N"], p["c"], Ds[i], p["ncp"]).ravel())
+        else:
+            outs.append(ofc.rx_cont(seg, p["L"], p["N"], p["c"], Ds[i], p["n_in"], lam=p["lam"], ola=p["ola"]))
+    return outs
+
+
+def oracle_adj(subbands, streams, Ds):
+    off, lens, P = stream_offsets(subbands)
+    outs = []
+    for i, s in enumerate(subbands):
+        p = P[i]
+        seg = streams[s["stream"]][off[i]:off[i] + p["Q"]]
+        if p["sync"]:
+            outs.append(ofc.rx_sync(seg, p["L"], p["N"], p["c"], Ds[i], p["ncp"], keep_cp=True))
+        else:
+            outs.append(ofc.rx_cont(seg, p["L"], p["N"], p["c"], Ds[i], p["n_in"], lam=p["lam"],
+                                    ola=not p["ola"]))
+    return outs
+
+
+# -------------------------------------------------- storage conversions --
+def to_device(a, io, device=0):
+    """complex128 numpy -> CUDA tensor of the plan's I/O type (RNE rounding)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a).astype(np.complex128))
+    if io == "c64":
+        return t.to(torch.complex64).to(f"cuda:{device}")
+    dt = torch.float16 if io == "f16" else torch.bfloat16
+    return torch.view_as_real(t).to(torch.float32).to(dt).contiguous().to(f"cuda:{device}")
+
+
+def from_device(t, io):
+    import torch
+    if io == "c64":
+        return t.cpu().numpy().astype(np.complex128)
+    f = t.to(torch.float32).cpu().numpy()
+    return (f[:, 0] + 1j * f[:, 1]).astype(np.complex128)
+
+
+def quantize(a, io):
+    """The rounding to_device applies, on the CPU (for storage/compute splits)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a).astype(np.complex128))
+    if io == "c64":
+        return t.to(torch.complex64).numpy().astype(np.complex128)
+    dt = torch.float16 if io == "f16" else torch.bfloat16
+    f = torch.view_as_real(t).to(torch.float32).to(dt).to(torch.float32).numpy()
+    return (f[:, 0] + 1j * f[:, 1]).astype(np.complex128)
+
+
+GATE_DB = {"c64": -100.0, "f16": -60.0, "bf16": -50.0}

@@ -1,0 +1,145 @@
+"""CPU-side checks of the C ABI: the library loads and exports every function
+include/fc.h declares; host-only plans reproduce the oracle's schedules and
+reject invalid descriptions with the documented status codes (no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from fc_cases import stream_offsets, sub_params
+from fcsynth import workloads as W
+from oracle import weights as ow
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fc.h")
+
+
+def _lib():
+    from paper_2008_00672_amd import fc
+    if not os.path.exists(fc.LIB_PATH):
+        pytest.skip("libfc.so not built")
+    return fc
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fc_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_match_header():
+    fc = _lib()
+    names = header_functions()
+    assert "fc_tx_synthesize" in names and "fc_rx_analyze" in names and "fc_set_weights" in names
+    raw = ctypes.CDLL(fc.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), "missing export " + n
+    assert set(names) == set(fc.EXPORTS), "binding and header disagree"
+
+
+def test_status_strings():
+    fc = _lib()
+    for code in range(0, -7, -1):
+        assert fc.lib().fc_status_str(code)
+    assert b"gfx950" in fc.lib().fc_version()
+
+
+def _plan(sbs, io="c64"):
+    fc = _lib()
+    return fc.Plan(sbs, io=io, device=-1)
+
+
+@pytest.mark.parametrize("wl", ["plain", "mixed", "rx8", "batched"])
+def test_layouts_match_oracle(wl):
+    fc = _lib()
+    sbs = {"plain": W.plain_tx_slot, "mixed": W.mixed_numerology, "rx8": lambda: W.rx_filterbank(28),
+           "batched": lambda: W.batched_carriers(24)}[wl]()[0]
+    p = _plan(sbs)
+    off, lens, P = stream_offsets(sbs)
+    op = fc.OP_RX if wl == "rx8" else fc.OP_TX
+    lo, hi = p.layout(op)
+    assert list(np.diff(hi)) == lens
+    for i, s in enumerate(sbs):
+        ncp, lcp, o = p.symbols(i)
+        assert ncp == P[i]["ncp"] and lcp == P[i]["lcp"] and o == off[i]
+        n_lo = s["n_symbols"] * s["n_short"] if (op == fc.OP_RX and P[i]["sync"]) else P[i]["n_in"]
+        assert lo[i + 1] - lo[i] == n_lo
+
+
+def test_default_weights_are_rc():
+    sbs, _ = W.mixed_numerology()
+    p = _plan(sbs)
+    for i, s in enumerate(sbs):
+        assert np.allclose(p.get_weights(i), ow.rc_weights(s["n_short"], s["n_active"], s["n_tb"]), atol=1e-7)
+
+
+def test_block_counts():
+    fc = _lib()
+    sbs, _ = W.plain_tx_slot()
+    assert _plan(sbs).stats(fc.OP_TX)["blocks"] == 31           # R = ceil((7680 + 128)/256)
+    sbs, _ = W.mixed_numerology()
+    assert _plan(sbs).stats(fc.OP_TX)["blocks"] == 2 * 14 + 2 * 28
+    # synchronised: two blocks per symbol; continuous: five for two symbols (L = 128)
+    s = W.subband(15, 2, 96, 8, 128, 1024, 0, "cont_ola")
+    assert _plan([s]).stats(fc.OP_TX)["blocks"] == 5
+    s = W.subband(15, 2, 96, 8, 128, 1024, 0, "sync_ola")
+    assert _plan([s]).stats(fc.OP_TX)["blocks"] == 4
+
+
+BAD = {
+    "short_not_pow2": (dict(n_short=96), "FC_E_UNSUPPORTED"),
+    "long_too_big": (dict(n_long=8192), "FC_E_UNSUPPORTED"),
+    "short_gt_long": (dict(n_short=4096, n_long=2048), "FC_E_SHAPE"),
+    "band_too_wide": (dict(n_active=500, n_tb=8), "FC_E_SHAPE"),
+    "center_out_of_range": (dict(center_bin=900), "FC_E_SHAPE"),
+    "odd_active": (dict(n_active=287), "FC_E_ARG"),
+    "bad_scs": (dict(scs_khz=20), "FC_E_ARG"),
+    "bad_mode": (dict(mode=7), "FC_E_ARG"),
+    "sync_quarter_overlap": (dict(mode="sync_ola", overlap=(1, 4)), "FC_E_UNSUPPORTED"),
+    "overlap_above_half": (dict(overlap=(3, 4)), "FC_E_UNSUPPORTED"),
+    "cont_fractional_cp": (dict(mode="cont_ols", n_short=64, n_active=40, n_tb=8), "FC_E_SHAPE"),
+    "sync_cp_too_long": (dict(mode="sync_ola", ncp_high=[600] * 14), "FC_E_SHAPE"),
+    "zero_symbols": (dict(n_symbols=0), "FC_E_ARG"),
+}
+CODES = {"FC_E_ARG": -1, "FC_E_SHAPE": -2, "FC_E_UNSUPPORTED": -3}
+
+
+@pytest.mark.parametrize("case", sorted(BAD))
+def test_validation(case):
+    fc = _lib()
+    patch, code = BAD[case]
+    s = dict(W.plain_tx_slot()[0][0])
+    s.update(patch)
+    with pytest.raises(fc.FcError) as ei:
+        fc.Plan([s], device=-1)
+    assert ei.value.status == CODES[code]
+
+
+def test_nonfinite_weights_rejected():
+    fc = _lib()
+    p = _plan(W.plain_tx_slot()[0])
+    w = np.ones(512, dtype=np.float32)
+    w[7] = np.nan
+    with pytest.raises(fc.FcError) as ei:
+        p.set_weights(0, w)
+    assert ei.value.status == -1
+    with pytest.raises(ValueError):
+        p.set_weights(0, np.ones(10))
+
+
+def test_compute_on_host_plan_is_state_error():
+    fc = _lib()
+    p = _plan(W.plain_tx_slot()[0])
+    st = fc.lib().fc_tx_synthesize(p._h, ctypes.c_void_p(1), ctypes.c_void_p(1), None)
+    assert st == -6
+
+
+def test_sync_ols_has_no_tx():
+    fc = _lib()
+    s = dict(W.rx_filterbank(14)[0][0])
+    p = _plan([s])
+    with pytest.raises(fc.FcError):
+        p.layout(fc.OP_TX)
+    p.layout(fc.OP_RX)

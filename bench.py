@@ -1,0 +1,378 @@
+"""Throughput of the batched mixed-precision FC filter banks on one MI355X.
+
+One step = one pass of the hot path over one batch of synthetic input:
+  TX: symbol-synchronised FC synthesis of 256 independent carriers of uneven
+      width (1-106 PRB), numerology (15/30/60 kHz) and long transform
+      (1024-4096), one slot each, FP16 I/Q storage, repeated over
+      --tx-batches slot-batches (one kernel launch);
+  RX: symbol-synchronised FC analysis of a 100 MHz / 30 kHz carrier (N = 4096)
+      into 8 subbands, one 10 ms frame each, BF16 I/Q storage, --rx-frames
+      frames (one kernel launch).
+value = (high-rate samples produced by TX + consumed by RX) / step time.
+The plain form (FP32, one plan and launch per carrier / per subband, no
+batching) is timed on the same work and reported beside it.
+
+Prints ONE JSON line. --gpus above 1 is refused (single-GPU build).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 excluded
+ALU_PEAK_TFLOPS = 78.6
+ALU_PEAK_PACKED_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tx-batches", type=int, default=32)
+    ap.add_argument("--rx-frames", type=int, default=100)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------ workloads ---
+def tx_workload(n_batches):
+    from fcsynth import workloads as W
+    sbs, meta = W.batched_carriers()
+    out = []
+    for b in range(n_batches):
+        for k, s in enumerate(sbs):
+            out.append(dict(s, stream=b * len(sbs) + k))
+    return sbs, out, meta
+
+
+def rx_workload(n_frames):
+    from fcsynth import workloads as W
+    sbs, meta = W.rx_filterbank()
+    out = []
+    for f in range(n_frames):
+        for s in sbs:
+            out.append(dict(s, stream=f))
+    return sbs, out, meta
+
+
+def tx_input(plan, sbs, meta):
+    """CP-OFDM input of one batch (complex128) from the plan's CP schedule."""
+    import fcsynth
+    rng = np.random.default_rng(meta["seed"])
+    xs = []
+    for i, s in enumerate(sbs):
+        _, lcp, _ = plan.symbols(i)
+        g = fcsynth.qam_grid(rng, meta["qam"], s["n_symbols"], s["n_active"])
+        xs.append(fcsynth.cp_ofdm(g, s["n_short"], lcp))
+    return xs
+
+
+def rx_input(plan, sbs, meta):
+    """One frame: the 8 subbands' 256-QAM CP-OFDM from one 4096-point IDFT per
+    symbol, placed where the plan expects the first useful sample, plus AWGN."""
+    import fcsynth
+    rng = np.random.default_rng(meta["seed"])
+    ncp, _, _ = plan.symbols(0)
+    grids = [fcsynth.qam_grid(rng, meta["qam"], s["n_symbols"], s["n_active"]) for s in sbs]
+    sig = fcsynth.cp_ofdm_highrate(grids, [s["center_bin"] for s in sbs], sbs[0]["n_long"], ncp)
+    lo, hi = plan.layout(1)
+    Q = int(hi[1] - hi[0])
+    N = sbs[0]["n_long"]
+    lead = N // 4 - ncp[0]
+    y = np.zeros(Q, dtype=complex)
+    y[lead:lead + len(sig)] = sig
+    p = np.mean(np.abs(sig) ** 2)
+    y += fcsynth.awgn(rng, Q, p * 10 ** (-meta["snr_db"] / 10))
+    return y
+
+
+def to_dev(a, io, reps=1):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if io == "c64":
+        d = t.to(torch.complex64)
+    else:
+        dt = torch.float16 if io == "f16" else torch.bfloat16
+        d = torch.view_as_real(t).to(torch.float32).to(dt).contiguous()
+    d = d.cuda()
+    if reps > 1:
+        d = d.repeat((reps,) + (1,) * (d.dim() - 1)).contiguous()
+    return d
+
+
+# ----------------------------------------------------- algorithmic cost ---
+def tx_cost(sbs, bytes_per_sample):
+    """Algorithmic bytes (input read once + output written once) and nominal
+    flops (5 L log2 L + 2 L + 5 N log2 N per block) of synchronised TX."""
+    from paper_2008_00672_amd import Plan, OP_TX
+    p = Plan(sbs, io="c64", device=-1)
+    lo, hi = p.layout(OP_TX)
+    flops = 0.0
+    for s in sbs:
+        L, N = s["n_short"], s["n_long"]
+        flops += 2 * s["n_symbols"] * (5 * L * math.log2(L) + 2 * L + 5 * N * math.log2(N))
+    return (lo[-1] + hi[-1]) * bytes_per_sample, flops, int(hi[-1])
+
+
+def rx_cost(sbs, bytes_per_sample):
+    from paper_2008_00672_amd import Plan, OP_RX
+    p = Plan(sbs, io="c64", device=-1)
+    lo, hi = p.layout(OP_RX)
+    N = sbs[0]["n_long"]
+    B = sbs[0]["n_symbols"]
+    flops = 2 * B * 5 * N * math.log2(N)
+    for s in sbs:
+        L = s["n_short"]
+        flops += 2 * B * (5 * L * math.log2(L) + 2 * L)
+    return (lo[-1] + hi[-1]) * bytes_per_sample, flops, int(hi[-1])
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("fc_kernels.hip", "fc_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2008_00672_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic(kernel, launches_per_step):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d["bytes_per_launch"]
+
+
+# ------------------------------------------------------------ CPU leg ---
+def cpu_baseline(budget_s, tx_sbs, tx_meta, gpu_tx_out, tx_plan_one, rx_sbs, rx_meta, gpu_rx_out, rx_plan_one,
+                 rx_in):
+    """Time the FP64 oracle on a bounded sample of the same work and check the
+    GPU outputs on that sample (EVM against the oracle on unquantised input)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from fc_cases import oracle_rx, oracle_tx
+    from oracle import metrics
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    xs = tx_input(tx_plan_one, tx_sbs, tx_meta)
+    lo, hi = tx_plan_one.layout(0)
+    t0 = time.time()
+    n_done, samples, evm_tx = 0, 0, []
+    order = np.argsort([s["n_long"] for s in tx_sbs])      # cheap carriers first
+    for k in order:
+        s = dict(tx_sbs[k], stream=0)
+        ref = oracle_tx([s], [xs[k]], [tx_plan_one.get_weights(k)])[0]
+        got = gpu_tx_out[hi[k]:hi[k + 1]]
+        evm_tx.append(metrics.err_db(got, ref))
+        samples += len(ref)
+        n_done += 1
+        if time.time() - t0 > budget_s * 0.6:
+            break
+    t_tx = time.time() - t0
+    # RX: first symbols of the frame, all 8 subbands
+    t1 = time.time()
+    B = 14
+    sub = [dict(s, n_symbols=B) for s in rx_sbs]
+    from paper_2008_00672_amd import Plan
+    ph = Plan(sub, io="c64", device=-1)
+    _, hh = ph.layout(1)
+    seg = rx_in[:int(hh[-1])]
+    refs = oracle_rx(sub, [seg], [rx_plan_one.get_weights(i) for i in range(len(rx_sbs))])
+    lo_rx, _ = rx_plan_one.layout(1)
+    evm_rx = []
+    for i, r in enumerate(refs):
+        got = gpu_rx_out[lo_rx[i]:lo_rx[i] + len(r)]
+        evm_rx.append(metrics.err_db(got, r))
+    t_rx = time.time() - t1
+    rate = (samples + len(seg)) / (t_tx + t_rx) / 1e6
+    return dict(value=rate, unit="Msamples/s", cores=threads, kind="oracle",
+                sample="FP64 dense-DFT oracle: TX of %d of the 256 carriers (one slot each) + RX of the first "
+                       "14 symbols of one 8-subband frame; %.1f s" % (n_done, t_tx + t_rx)), \
+        dict(tx_max=float(np.max(evm_tx)), tx_mean=float(np.mean(evm_tx)), rx_max=float(np.max(evm_rx)),
+             tx_carriers=n_done)
+
+
+# ------------------------------------------------------------------ main ---
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        return 2
+    import torch
+    from paper_2008_00672_amd import Plan, OP_RX, OP_TX
+
+    if args.copy_calib:
+        n = 256 << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}))
+        return 0
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    # ---------------- batched TX ----------------
+    tx_one, tx_all, tx_meta = tx_workload(args.tx_batches)
+    t = time.time()
+    ptx = Plan(tx_all, io="f16", device=0)
+    ptx1 = Plan(tx_one, io="f16", device=0)
+    xs = tx_input(ptx1, tx_one, tx_meta)
+    x_dev = to_dev(np.concatenate(xs), "f16", reps=args.tx_batches)
+    lo, hi = ptx.layout(OP_TX)
+    assert x_dev.shape[0] == lo[-1]
+    y_dev = ptx.empty(int(hi[-1]))
+    log("TX plan: %d carriers, %s, %.1f s" % (len(tx_all), ptx.stats(OP_TX), time.time() - t))
+
+    # ---------------- batched RX ----------------
+    rx_one, rx_all, rx_meta = rx_workload(args.rx_frames)
+    t = time.time()
+    prx = Plan(rx_all, io="bf16", device=0)
+    prx1 = Plan(rx_one, io="bf16", device=0)
+    rx_in = rx_input(prx1, rx_one, rx_meta)
+    r_dev = to_dev(rx_in, "bf16", reps=args.rx_frames)
+    lo_r, hi_r = prx.layout(OP_RX)
+    assert r_dev.shape[0] == hi_r[-1]
+    z_dev = prx.empty(int(lo_r[-1]))
+    log("RX plan: %d frames, %s, %.1f s" % (args.rx_frames, prx.stats(OP_RX), time.time() - t))
+
+    def step():
+        ptx.tx(x_dev, y_dev, stream)
+        prx.rx(r_dev, z_dev, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ptx.tx(x_dev, y_dev, stream)
+        ev[k][1].record(stream)
+        prx.rx(r_dev, z_dev, stream)
+        ev[k][2].record(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    tx_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    rx_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    tx_bytes, tx_flops, tx_samples = tx_cost(tx_all, 4)
+    rx_bytes, rx_flops, rx_samples = rx_cost(rx_all, 4)
+    value = (tx_samples + rx_samples) / (ms * 1e-3) / 1e6
+    log("step %.3f ms: TX %.3f ms (%.0f GB/s, %.1f TFLOP/s), RX %.3f ms (%.0f GB/s, %.1f TFLOP/s)" % (
+        ms, tx_ms, tx_bytes / tx_ms / 1e6, tx_flops / tx_ms / 1e9, rx_ms, rx_bytes / rx_ms / 1e6,
+        rx_flops / rx_ms / 1e9))
+
+    # dominant kernel
+    if tx_ms >= rx_ms:
+        dk, d_ms, d_bytes, d_flops = "fc_tx_kernel", tx_ms, tx_bytes, tx_flops
+    else:
+        dk, d_ms, d_bytes, d_flops = "fc_rx_kernel", rx_ms, rx_bytes, rx_flops
+    ai = d_flops / d_bytes
+    ridge = ALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    hbm_gbs = d_bytes / d_ms / 1e6
+    alu_tf = d_flops / d_ms / 1e9
+    if ai > ridge:
+        roof = {"bound": "alu", "achieved": round(alu_tf, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(alu_tf / ALU_PEAK_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
+    roof["traffic"] = traffic(dk, 1)
+    roof["kernel"] = dk
+    roof["hbm_gbs"] = round(hbm_gbs, 1)
+    roof["hbm_frac"] = round(hbm_gbs / HBM_PEAK_GBS, 4)
+    roof["alu_frac_packed_peak"] = round(alu_tf / ALU_PEAK_PACKED_TFLOPS, 4)
+    roof["flop_per_byte"] = round(ai, 2)
+
+    # ---------------- plain FP32 form ----------------
+    plain = None
+    if not args.no_plain:
+        plans = [Plan([dict(s, stream=0)], io="c64", device=0) for s in tx_one]
+        xin = [to_dev(x, "c64") for x in xs]
+        outs = [p.empty(int(p.layout(OP_TX)[1][-1])) for p in plans]
+        rplans = [Plan([dict(s, stream=0)], io="c64", device=0) for s in rx_one]
+        rin = to_dev(rx_in, "c64")
+        routs = [p.empty(int(p.layout(OP_RX)[0][-1])) for p in rplans]
+
+        def plain_step():
+            for p, xi, o in zip(plans, xin, outs):
+                p.tx(xi, o, stream)
+            for p, o in zip(rplans, routs):
+                p.rx(rin, o, stream)
+        for _ in range(2):
+            plain_step()
+        torch.cuda.synchronize()
+        n_plain = max(2, args.steps // 4)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(n_plain):
+            plain_step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        pms = a.elapsed_time(b) / n_plain
+        p_samples = tx_samples / args.tx_batches + rx_samples / args.rx_frames
+        plain = {"value": round(p_samples / (pms * 1e-3) / 1e6, 1), "unit": "Msamples/s",
+                 "ms_per_batch": round(pms, 3),
+                 "form": "FP32 I/O, one plan and one launch per carrier (TX) / per subband (RX), "
+                         "one slot-batch + one frame"}
+        log("plain: %.3f ms per (1 TX batch + 1 RX frame) -> %.0f Msamples/s" % (pms, plain["value"]))
+
+    # ---------------- CPU oracle + EVM on a sample ----------------
+    cpu, evm = None, None
+    if not args.no_cpu:
+        import torch as _t
+        yh = y_dev[:int(ptx1.layout(OP_TX)[1][-1])].to(_t.float32).cpu().numpy()
+        zh = z_dev[:int(prx1.layout(OP_RX)[0][-1])].to(_t.float32).cpu().numpy()
+        cpu, evm = cpu_baseline(args.cpu_seconds, tx_one, tx_meta, yh[:, 0] + 1j * yh[:, 1], ptx1,
+                                rx_one, rx_meta, zh[:, 0] + 1j * zh[:, 1], prx1, rx_in)
+        cpu["value"] = round(cpu["value"], 3)
+        log("cpu oracle %.3f Msamples/s on %d threads; EVM vs FP64: %s" % (cpu["value"], cpu["cores"], evm))
+
+    out = {
+        "metric": "FC-OFDM Msamples/s on 1 GPU, batched vs plain, at EVM <= -50 dB vs FP64",
+        "value": round(value, 1), "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 compute, f16/bf16 storage", "data": "synthetic",
+        "config": {"workload": "batched FC TX (256 uneven carriers x %d slot-batches, FP16 I/Q) + batched FC RX "
+                               "(8 subbands of a 100 MHz 30 kHz carrier x %d frames, BF16 I/Q)"
+                               % (args.tx_batches, args.rx_frames),
+                   "tx_samples": tx_samples, "rx_samples": rx_samples, "tx_ms": round(tx_ms, 4),
+                   "rx_ms": round(rx_ms, 4)},
+        "roofline": roof, "plain": plain, "evm_db": evm, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -11,7 +11,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfc.so")
 
-SOURCES = ["fc_kernels.hip", "fc_plan.cpp"]
+# (source, extra defines): the device code is built once per I/O storage type
+UNITS = [("fc_kern_io.hip", ["-DFC_IO=0"]), ("fc_kern_io.hip", ["-DFC_IO=1"]), ("fc_kern_io.hip", ["-DFC_IO=2"]),
+         ("fc_launch.cpp", []), ("fc_plan.cpp", [])]
 
 # Packed FP32 VALU forms are kept out of the generated code; the compiler
 # otherwise forms them from float2 arithmetic.
@@ -27,16 +29,35 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+def build(verbose=False, jobs=None):
+    """Compile every unit to an object (in parallel), then link libfc.so."""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs, objs = [], []
+    for k, (src, defs) in enumerate(UNITS):
+        obj = os.path.join(objdir, "%d_%s.o" % (k, os.path.splitext(src)[0]))
+        cmd = [hipcc()] + HIP_FLAGS + defs + ["-I", os.path.join(ROOT, "include"), "-c", "-o", obj,
+                                              os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+        objs.append(obj)
+    failed = False
+    for cmd, p in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            failed = True
+            sys.stderr.write(" ".join(cmd) + "\n" + out + err)
+    if failed:
+        raise RuntimeError("hipcc failed building libfc.so")
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
+    cmd = [hipcc()] + HIP_FLAGS + ["-shared", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfc.so")
+        raise RuntimeError("hipcc failed linking libfc.so")
     os.replace(tmp, LIB)
     return LIB
 

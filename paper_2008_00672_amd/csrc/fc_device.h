@@ -1,0 +1,677 @@
+// Device code of the fast-convolution (FC) filter banks for gfx950.
+//
+// One workgroup (256 threads, 4 wave64) processes one task: a run of
+// consecutive FC blocks of one processing group (TX) or one block (RX).
+// Transforms are Stockham FFTs held in LDS: every pass loads R values per
+// butterfly into registers, applies the inter-pass twiddles (FP32 table built
+// in FP64 on the host), runs a radix-R (2/4/8/16) DFT in registers and writes
+// back in place after a barrier. Up to 16 complex values per thread, so one
+// workgroup holds transforms of up to 4096 points (or batches of shorter ones
+// with the same total), one wave up to 1024. Transform size, batch count and
+// radix plan are compile-time, so all LDS offsets of a thread are one base
+// register plus immediates. The first pass reads through a load functor
+// (global memory or another LDS array) and the last pass hands its results
+// to a store functor in registers, so segmentation, windowing, bin mapping,
+// weighting and the overlap-add / overlap-save combination are fused into the
+// transforms.
+//
+// Paper: Yli-Kaakinen et al., arXiv 2008.00672. TX follows the block operator
+// W_N^{-1} M(phi) D P^(L/2) W_L A (Sec. III-B) and its symbol-synchronised
+// form (Sec. III-C..III-E); RX follows W_L^{-1} P^(-L/2) D M^T W_N (Sec. IV).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "fc_internal.h"
+
+namespace fcx {
+
+// --------------------------------------------------------------- complex --
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by exp(DIR * j pi/2): DIR = -1 (forward) gives -j, DIR = +1 gives +j
+template <int DIR>
+__device__ __forceinline__ float2 mulj(float2 a) {
+  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+template <int DIR>
+__device__ __forceinline__ float2 cmulk(float2 a, float c, float s) {  // a * (c + DIR j s)
+  return DIR < 0 ? make_float2(a.x * c + a.y * s, a.y * c - a.x * s)
+                 : make_float2(a.x * c - a.y * s, a.y * c + a.x * s);
+}
+
+// ---------------------------------------------------- register DFTs ------
+// X[k] = sum_n v[n] exp(DIR j 2 pi n k / R), in place, natural order.
+template <int R, int DIR> struct Dft;
+
+template <int DIR> struct Dft<2, DIR> {
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  float2 t2 = cadd(a1, a3), t3 = mulj<DIR>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <int DIR> struct Dft<4, DIR> {
+  static __device__ __forceinline__ void run(float2* v) { dft4<DIR>(v[0], v[1], v[2], v[3]); }
+};
+
+template <int DIR> struct Dft<8, DIR> {
+  static __device__ __forceinline__ void run(float2* v) {
+    constexpr float h = 0.70710678118654752440f;
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    o1 = cmulk<DIR>(o1, h, h);                 // W8^1
+    o2 = mulj<DIR>(o2);                        // W8^2
+    o3 = cmulk<DIR>(o3, -h, h);                // W8^3
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+  }
+};
+
+template <int DIR> struct Dft<16, DIR> {
+  // 16 = 4 x 4: X[k1 + 4 k2] = sum_n2 W4^(n2 k2) W16^(n2 k1) sum_n1 v[n2 + 4 n1] W4^(n1 k1)
+  static __device__ __forceinline__ void run(float2* v) {
+    constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+    constexpr float h = 0.70710678118654752440f;
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<DIR>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+    // after the first layer, v[n2 + 4 k1] holds B[n2][k1]
+    v[5] = cmulk<DIR>(v[5], c1, s1);           // n2=1,k1=1: W16^1
+    v[9] = cmulk<DIR>(v[9], h, h);             // n2=1,k1=2: W16^2
+    v[13] = cmulk<DIR>(v[13], s1, c1);         // n2=1,k1=3: W16^3
+    v[6] = cmulk<DIR>(v[6], h, h);             // n2=2,k1=1: W16^2
+    v[10] = mulj<DIR>(v[10]);                  // n2=2,k1=2: W16^4
+    v[14] = cmulk<DIR>(v[14], -h, h);          // n2=2,k1=3: W16^6
+    v[7] = cmulk<DIR>(v[7], s1, c1);           // n2=3,k1=1: W16^3
+    v[11] = cmulk<DIR>(v[11], -h, h);          // n2=3,k1=2: W16^6
+    v[15] = cmulk<DIR>(v[15], -c1, -s1);       // n2=3,k1=3: W16^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4<DIR>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // now v[4 k1 + k2] holds X[k1 + 4 k2]: transpose to natural order
+    float2 t[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = t[i];
+  }
+};
+
+// ------------------------------------------------------------ pass plan ---
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+constexpr int npass(int P) { return P <= 16 ? 1 : (P <= 256 ? 2 : 3); }
+constexpr int radix_of(int P, int s) {
+  // 2..16: one pass; 32..256: two; 512..4096: three
+  return P <= 16 ? P
+       : P == 32 ? (s == 0 ? 8 : 4)
+       : P == 64 ? 8
+       : P == 128 ? (s == 0 ? 16 : 8)
+       : P == 256 ? 16
+       : P == 512 ? 8
+       : P == 1024 ? (s < 2 ? 16 : 4)
+       : P == 2048 ? (s < 2 ? 16 : 8)
+       : 16;
+}
+
+// LDS layout of the transform buffers between passes: one pad slot after
+// every 32 elements, so the strided butterfly writes of the early passes
+// spread over the banks. Buffers of n elements take lds_elems(n) slots.
+__device__ __forceinline__ constexpr int pad(int e) { return e + (e >> 5); }
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NT>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (NT == kThreads) __syncthreads(); else wave_sync();
+}
+
+// One Stockham pass over P-point transforms, 2^LOGBT of them interleaved
+// (element i of transform b at index i * 2^LOGBT + b), run by NT threads.
+// NS is the product of the radices of the previous passes.
+template <int NT, int P, int LOGBT, int R, int NS, int DIR, bool FIRST, bool LAST, class Load, class Store>
+__device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load& load, Store& store,
+                                         const float2* __restrict__ tw) {
+  constexpr int NB = P / R;
+  constexpr int BT = 1 << LOGBT;
+  constexpr int TOTAL = NB * BT;
+  constexpr int MAXIT = (TOTAL + NT - 1) / NT;
+  static_assert(MAXIT * R <= 16, "at most 16 complex values per thread");
+  float2 v[MAXIT][R];
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int g = tid + it * NT;
+    if (TOTAL % NT == 0 || g < TOTAL) {
+      const int b = g & (BT - 1), j = g >> LOGBT;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if constexpr (FIRST)
+          v[it][r] = load(j + r * NB, b);
+        else
+          v[it][r] = buf[pad(((j + r * NB) << LOGBT) + b)];
+      }
+    }
+  }
+  group_sync<NT>();
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int g = tid + it * NT;
+    if (TOTAL % NT == 0 || g < TOTAL) {
+      const int b = g & (BT - 1), j = g >> LOGBT;
+      const int k = j & (NS - 1);
+      if constexpr (!FIRST) {
+        constexpr int STRIDE = kTwiddleN / (NS * R);
+        const int ks = k * STRIDE;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[ks * r];
+          if (DIR > 0) w.y = -w.y;
+          v[it][r] = cmul(v[it][r], w);
+        }
+      }
+      Dft<R, DIR>::run(v[it]);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) store(it * R + r, ((j + r * NB) << LOGBT) + b, v[it][r]);
+      } else {
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[pad(((base + r * NS) << LOGBT) + b)] = v[it][r];
+      }
+    }
+  }
+  if constexpr (!LAST) group_sync<NT>();
+}
+
+// Whole transform: DIR = -1 forward DFT, +1 unnormalised inverse, of 2^LOGBT
+// interleaved P-point transforms. The caller provides a barrier before the
+// call when `buf`, or what `load` reads, was written by other threads.
+template <int NT, int P, int LOGBT, int DIR, class Load, class Store>
+__device__ __forceinline__ void fft_run(float2* buf, int tid, Load& load, Store& store,
+                                        const float2* __restrict__ tw) {
+  constexpr int NP = npass(P);
+  constexpr int R0 = radix_of(P, 0), R1 = radix_of(P, 1), R2 = radix_of(P, 2);
+  fft_pass<NT, P, LOGBT, R0, 1, DIR, true, NP == 1>(buf, tid, load, store, tw);
+  if constexpr (NP >= 2) fft_pass<NT, P, LOGBT, R1, R0, DIR, false, NP == 2>(buf, tid, load, store, tw);
+  if constexpr (NP >= 3) fft_pass<NT, P, LOGBT, R2, R0 * R1, DIR, false, true>(buf, tid, load, store, tw);
+}
+
+// Output position of register slot s of the last pass (-1: slot unused).
+template <int NT, int P, int LOGBT>
+__device__ __forceinline__ int last_pos(int s, int tid) {
+  constexpr int R = radix_of(P, npass(P) - 1);
+  constexpr int NB = P / R;
+  constexpr int TOTAL = NB << LOGBT;
+  const int it = s / R, r = s % R;
+  const int g = tid + it * NT;
+  if (g >= TOTAL) return -1;
+  const int b = g & ((1 << LOGBT) - 1), j = g >> LOGBT;
+  return ((j + r * NB) << LOGBT) + b;
+}
+
+// ------------------------------------------------------------------- I/O --
+// Interleaved I/Q storage; element pointers are formed once per block from the
+// uniform 64-bit offsets, per-sample indices are 32-bit.
+template <int IO> struct Io;
+template <> struct Io<IO_C64> {
+  using T = float2;
+  static __device__ __forceinline__ float2 ld(const T* p, int i) { return p[i]; }
+  static __device__ __forceinline__ void st(T* p, int i, float2 v) { p[i] = v; }
+};
+template <> struct Io<IO_F16> {
+  using T = __half2;
+  static __device__ __forceinline__ float2 ld(const T* p, int i) { return __half22float2(p[i]); }
+  static __device__ __forceinline__ void st(T* p, int i, float2 v) { p[i] = __float22half2_rn(v); }
+};
+__device__ __forceinline__ uint32_t f2bf_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;        // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+template <> struct Io<IO_BF16> {
+  using T = uint32_t;
+  static __device__ __forceinline__ float2 ld(const T* p, int i) {
+    const uint32_t u = p[i];
+    return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+  }
+  static __device__ __forceinline__ void st(T* p, int i, float2 v) { p[i] = f2bf_rne(v.x) | (f2bf_rne(v.y) << 16); }
+};
+
+template <int IO>
+__device__ __forceinline__ const typename Io<IO>::T* at(const void* p, int64_t off) {
+  return reinterpret_cast<const typename Io<IO>::T*>(p) + off;
+}
+template <int IO>
+__device__ __forceinline__ typename Io<IO>::T* at(void* p, int64_t off) {
+  return reinterpret_cast<typename Io<IO>::T*>(p) + off;
+}
+template <int IO>
+__device__ __forceinline__ void put(typename Io<IO>::T* p, int i, float2 v, bool acc) {
+  if (acc) v = cadd(v, Io<IO>::ld(p, i));
+  Io<IO>::st(p, i, v);
+}
+
+// ------------------------------------------------------------- functors ---
+// Low-rate segment: block sample i is x[i] inside [lo, hi), else 0.
+template <int IO> struct LoadSeg {
+  const typename Io<IO>::T* x; int lo, hi;
+  __device__ __forceinline__ float2 operator()(int i, int) const {
+    return (i >= lo && i < hi) ? Io<IO>::ld(x, i) : make_float2(0.f, 0.f);
+  }
+};
+
+// Natural-order LDS read (first pass reading an LDS spectrum).
+struct LoadLds {
+  const float2* s;
+  __device__ __forceinline__ float2 operator()(int i, int) const { return s[i]; }
+};
+
+// TX, pruned long IFFT: short-FFT bin u -> residue rho = (u + c) mod L of the
+// band, weighted by D[p] (p = (u + L/2) mod L, the fftshifted index) and the
+// block phase.
+template <int L> struct StoreBand {
+  float2* V; const float* D; float2 ph; int c;
+  __device__ __forceinline__ void operator()(int, int u, float2 v) const {
+    const int p = (u + (L >> 1)) & (L - 1);
+    V[(u + c) & (L - 1)] = cscale(cmul(v, ph), D[p]);
+  }
+};
+
+// TX, pruned long IFFT first pass: sub-transform b (output samples t = a*I + b)
+// of residue rho takes V[rho] * exp(+j 2 pi q b / N), q the band bin of rho.
+template <int L, int N> struct LoadPruned {
+  const float2* V; const float2* tw; int q0;
+  __device__ __forceinline__ float2 operator()(int rho, int b) const {
+    const int q = (q0 + ((rho - q0) & (L - 1))) & (N - 1);
+    float2 w = tw[((q * b) & (N - 1)) * (kTwiddleN / N)];
+    w.y = -w.y;
+    return cmul(V[rho], w);
+  }
+};
+
+// TX, full long IFFT: add the weighted band into the N-bin spectrum.
+template <int N> struct StoreAddLong {
+  float2* S; const float* D; float2 ph; int L, q0;
+  __device__ __forceinline__ void operator()(int, int u, float2 v) const {
+    const int p = (u + (L >> 1)) & (L - 1);
+    const int q = (q0 + p) & (N - 1);
+    S[q] = cadd(S[q], cscale(cmul(v, ph), D[p]));
+  }
+};
+
+// TX epilogue, phase 1 (inside the last pass): OLA carry-in for block samples
+// t < pth; results stay in registers until phase 2.
+struct TxEpi {
+  const float2* pend; int pth;
+  float2 val[16];
+  __device__ __forceinline__ void operator()(int slot, int t, float2 v) {
+    if (t < pth) v = cadd(v, pend[t]);
+    val[slot] = v;
+  }
+};
+
+// RX: long-FFT result into the LDS spectrum (natural order).
+struct StoreLds {
+  float2* s;
+  __device__ __forceinline__ void operator()(int, int t, float2 v) const { s[t] = v; }
+};
+
+// High-rate segment with an input window [lo, hi).
+template <int IO> struct LoadHigh {
+  const typename Io<IO>::T* x; int lo, hi;
+  __device__ __forceinline__ float2 operator()(int i, int) const {
+    return (i >= lo && i < hi) ? Io<IO>::ld(x, i) : make_float2(0.f, 0.f);
+  }
+};
+
+// RX short IFFT first pass: bin u of the subband (inverse shift) gathers long
+// bin q = (q0 + p) mod N, p = (u + L/2) mod L, weighted by D[p] and conj phase.
+template <int L, int N> struct LoadGather {
+  const float2* S; const float* D; float2 ph; int q0;
+  __device__ __forceinline__ float2 operator()(int u, int) const {
+    const int p = (u + (L >> 1)) & (L - 1);
+    return cscale(cmul(S[(q0 + p) & (N - 1)], ph), D[p]);
+  }
+};
+
+// RX output: keep window [lo, hi) of the low-rate block.
+template <int IO> struct StoreLow {
+  typename Io<IO>::T* out; int lo, hi; bool acc;
+  __device__ __forceinline__ void operator()(int, int i, float2 v) const {
+    if (i >= lo && i < hi) put<IO>(out, i, v, acc);
+  }
+};
+
+// ------------------------------------------------------------- TX tasks ---
+// Block-local 32-bit view of the OLA/OLS bookkeeping of one TX block.
+struct TxWin {
+  int pth;    // samples t < pth add the carry of the previous block
+  int cth;    // samples t >= cth go to the carry of the next block
+  int wlo, whi;   // samples written to the output
+};
+
+__device__ __forceinline__ TxWin tx_window(const BlockDesc& B, const TaskDesc& T, int64_t prev_end,
+                                           int64_t next_start, int n) {
+  TxWin w;
+  w.pth = prev_end > B.t0 ? (int)(prev_end - B.t0) : 0;
+  w.cth = next_start < B.t0 + n ? (int)(next_start - B.t0) : n;
+  int64_t lo = T.own_lo - B.t0, hi = T.own_hi - B.t0;
+  lo = lo > B.hlo ? lo : B.hlo;
+  hi = hi < B.hhi ? hi : B.hhi;
+  if (hi < lo) hi = lo;
+  w.wlo = (int)(lo < 0 ? 0 : (lo > n ? n : lo));
+  w.whi = (int)(hi < 0 ? 0 : (hi > n ? n : hi));
+  return w;
+}
+
+// Epilogue phase 2 (after a barrier): OLA carry-out or write the owned samples.
+template <int IO, int NT, int P, int LOGBT>
+__device__ __forceinline__ void tx_epilogue(const TxEpi& ep, float2* pend, const TxWin& w,
+                                            typename Io<IO>::T* ob, bool acc) {
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int t = last_pos<NT, P, LOGBT>(s, threadIdx.x);
+    if (t < 0) continue;
+    if (t >= w.cth) pend[t - w.cth] = ep.val[s];
+    else if (t >= w.wlo && t < w.whi) put<IO>(ob, t, ep.val[s], acc);
+  }
+}
+
+template <int IO>
+__device__ __forceinline__ void zero_span(void* out, int64_t lo, int64_t hi) {
+  if (hi <= lo) return;
+  typename Io<IO>::T* p = at<IO>(out, lo);
+  const int n = (int)(hi - lo);
+  for (int i = threadIdx.x; i < n; i += kThreads) Io<IO>::st(p, i, make_float2(0.f, 0.f));
+}
+
+// Single-subband group, N = L * 2^LOGI: short FFT (one wave when L <= 1024),
+// then the long IFFT evaluated as 2^LOGI interleaved L-point IFFTs of the
+// twiddled band (outputs land in natural order).
+template <int IO, int L, int LOGI>
+__global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
+  constexpr int N = L << LOGI;
+  extern __shared__ float2 smem[];
+  const int task = blockIdx.x;
+  if (task >= a.n_task) return;
+  const TaskDesc T = a.task[task];
+  const GroupDesc G = a.grp[T.group];
+  if (!T.accumulate) {
+    zero_span<IO>(a.out, T.z0_lo, T.z0_hi);
+    zero_span<IO>(a.out, T.z1_lo, T.z1_hi);
+  }
+  const SbDesc S = a.sb[G.sb_first];
+  float2* buf = smem;                       // short FFT, band V (first L), batched IFFT
+  float2* pend = smem + lds_elems(N);       // OLA carry, up to N/2 points
+  const float* D = a.weights + S.w_off;
+  const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
+  const int tid = threadIdx.x;
+  int64_t prev_end = INT64_MIN;
+  for (int bi = 0; bi < T.blk_count; ++bi) {
+    const BlockDesc B = a.blk[T.blk_first + bi];
+    const BlockSb Z = a.bsb[B.bs];
+    const int64_t next_start =
+        (T.ola && bi + 1 < T.blk_count) ? a.blk[T.blk_first + bi + 1].t0 : INT64_MAX;
+    const TxWin w = tx_window(B, T, prev_end, next_start, N);
+    LoadSeg<IO> ld{at<IO>(a.in, Z.x0), Z.lo, Z.hi};
+    StoreBand<L> sb{buf, D, make_float2(Z.ph.x, Z.ph.y), S.c};
+    __syncthreads();
+    if constexpr (L <= 1024) {
+      if (tid < 64) fft_run<64, L, 0, -1>(buf, tid, ld, sb, tw);
+    } else {
+      fft_run<kThreads, L, 0, -1>(buf, tid, ld, sb, tw);
+    }
+    __syncthreads();
+    LoadPruned<L, N> lp{buf, tw, S.q0};
+    TxEpi ep;
+    ep.pend = pend; ep.pth = w.pth;
+    fft_run<kThreads, L, LOGI, +1>(buf, tid, lp, ep, tw);
+    __syncthreads();
+    tx_epilogue<IO, kThreads, L, LOGI>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0);
+    prev_end = T.ola ? B.t0 + N : INT64_MIN;
+  }
+}
+
+// Several subbands share the long IFFT: their weighted bands are added into
+// one N-bin spectrum, then a full N-point IFFT.
+template <int IO, int NL>
+__global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int lmax) {
+  extern __shared__ float2 smem[];
+  const int task = blockIdx.x;
+  if (task >= a.n_task) return;
+  const TaskDesc T = a.task[task];
+  const GroupDesc G = a.grp[T.group];
+  if (!T.accumulate) {
+    zero_span<IO>(a.out, T.z0_lo, T.z0_hi);
+    zero_span<IO>(a.out, T.z1_lo, T.z1_hi);
+  }
+  float2* S = smem;                                  // N-bin spectrum, then the in-place IFFT
+  float2* bs = smem + lds_elems(NL);                 // short FFT scratch
+  float2* pend = bs + lds_elems(lmax);               // OLA carry (N/2)
+  const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
+  const int tid = threadIdx.x;
+  int64_t prev_end = INT64_MIN;
+  for (int bi = 0; bi < T.blk_count; ++bi) {
+    const BlockDesc B = a.blk[T.blk_first + bi];
+    const int64_t next_start =
+        (T.ola && bi + 1 < T.blk_count) ? a.blk[T.blk_first + bi + 1].t0 : INT64_MAX;
+    const TxWin w = tx_window(B, T, prev_end, next_start, NL);
+    __syncthreads();
+    for (int i = tid; i < NL; i += kThreads) S[i] = make_float2(0.f, 0.f);
+    for (int m = 0; m < G.n_sb; ++m) {
+      const SbDesc Sb = a.sb[G.sb_first + m];
+      const BlockSb Z = a.bsb[B.bs + m];
+      LoadSeg<IO> ld{at<IO>(a.in, Z.x0), Z.lo, Z.hi};
+      StoreAddLong<NL> st{S, a.weights + Sb.w_off, make_float2(Z.ph.x, Z.ph.y), Sb.L, Sb.q0};
+      __syncthreads();
+      switch (Sb.L) {
+#define FC_SHORT(LL) case LL: if constexpr (LL <= NL) fft_run<kThreads, LL, 0, -1>(bs, tid, ld, st, tw); break;
+        FC_SHORT(16) FC_SHORT(32) FC_SHORT(64) FC_SHORT(128) FC_SHORT(256) FC_SHORT(512)
+        FC_SHORT(1024) FC_SHORT(2048) FC_SHORT(4096)
+#undef FC_SHORT
+        default: break;
+      }
+    }
+    __syncthreads();
+    LoadLds ls{S};
+    TxEpi ep;
+    ep.pend = pend; ep.pth = w.pth;
+    fft_run<kThreads, NL, 0, +1>(S, tid, ls, ep, tw);
+    __syncthreads();
+    tx_epilogue<IO, kThreads, NL, 0>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0);
+    prev_end = T.ola ? B.t0 + NL : INT64_MIN;
+  }
+}
+
+// ------------------------------------------------------------- RX tasks ---
+// One block per task: the long FFT on the whole workgroup, then every subband's
+// gather + short IFFT. Subbands with L <= 1024 run as one-wave transforms, the
+// wave chosen by the planner (balanced over the four waves); longer ones use
+// the whole workgroup afterwards.
+template <int IO, int NL>
+__global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax) {
+  extern __shared__ float2 smem[];
+  // consecutive tasks (blocks sharing half of their input) go to the same XCD:
+  // the dispatcher places workgroup i on XCD i mod 8
+  const int n = gridDim.x;
+  int task = blockIdx.x;
+  if ((n & 7) == 0) task = (blockIdx.x & 7) * (n >> 3) + (blockIdx.x >> 3);
+  if (task >= a.n_task) return;
+  const TaskDesc T = a.task[task];
+  const GroupDesc G = a.grp[T.group];
+  float2* S = smem;                                        // long spectrum (N)
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  float2* ws = smem + lds_elems(NL) + wave * lds_elems(wmax);   // this wave's scratch
+  float2* bs = smem + lds_elems(NL);                       // workgroup scratch (long subbands)
+  const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
+  for (int bi = 0; bi < T.blk_count; ++bi) {
+    const BlockDesc B = a.blk[T.blk_first + bi];
+    LoadHigh<IO> lh{at<IO>(a.in, B.t0), B.hlo, B.hhi};
+    StoreLds sl{S};
+    __syncthreads();
+    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sl, tw);
+    __syncthreads();
+    bool any_long = false;
+    for (int m = 0; m < G.n_sb; ++m) {
+      const SbDesc Sb = a.sb[G.sb_first + m];
+      if (Sb.wave < 0) { any_long = true; continue; }
+      if (Sb.wave != wave) continue;
+      const BlockSb Z = a.bsb[B.bs + m];
+      const float* D = a.weights + Sb.w_off;
+      const float2 ph = make_float2(Z.ph.x, Z.ph.y);
+      StoreLow<IO> so{at<IO>(a.out, Z.x0), Z.lo, Z.hi, T.accumulate != 0};
+      wave_sync();
+      switch (Sb.L) {
+#define FC_SHORT(LL)                                                   \
+  case LL:                                                             \
+    if constexpr (LL <= NL) {                                          \
+      LoadGather<LL, NL> lg{S, D, ph, Sb.q0};                          \
+      fft_run<64, LL, 0, +1>(ws, lane, lg, so, tw);                    \
+    }                                                                  \
+    break;
+        FC_SHORT(16) FC_SHORT(32) FC_SHORT(64) FC_SHORT(128) FC_SHORT(256) FC_SHORT(512) FC_SHORT(1024)
+#undef FC_SHORT
+        default: break;
+      }
+    }
+    if (any_long) {
+      for (int m = 0; m < G.n_sb; ++m) {
+        const SbDesc Sb = a.sb[G.sb_first + m];
+        if (Sb.wave >= 0) continue;
+        const BlockSb Z = a.bsb[B.bs + m];
+        const float* D = a.weights + Sb.w_off;
+        const float2 ph = make_float2(Z.ph.x, Z.ph.y);
+        StoreLow<IO> so{at<IO>(a.out, Z.x0), Z.lo, Z.hi, T.accumulate != 0};
+        __syncthreads();
+        switch (Sb.L) {
+#define FC_SHORT(LL)                                                   \
+  case LL:                                                             \
+    if constexpr (LL <= NL && LL > 1024) {                             \
+      LoadGather<LL, NL> lg{S, D, ph, Sb.q0};                          \
+      fft_run<kThreads, LL, 0, +1>(bs, tid, lg, so, tw);               \
+    }                                                                  \
+    break;
+          FC_SHORT(2048) FC_SHORT(4096)
+#undef FC_SHORT
+          default: break;
+        }
+      }
+    }
+  }
+}
+
+template <int IO>
+__global__ __launch_bounds__(kThreads) void fc_zero_kernel(void* out, int64_t n) {
+  typename Io<IO>::T* p = at<IO>(out, 0);
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
+    Io<IO>::st(p + i, 0, make_float2(0.f, 0.f));
+}
+
+// ------------------------------------------------------ per-I/O dispatch ---
+// Kernel classes: 0 = TX pruned (size = L, aux = log2 I), 1 = TX full
+// (size = N, aux = largest L), 2 = RX (size = N, aux = largest one-wave L).
+template <int IO, int L>
+hipError_t launch_pruned(const LaunchArgs& a, int logi, size_t lds, hipStream_t s, dim3 grid) {
+  dim3 block(kThreads);
+  switch (logi) {
+#define FC_LI(LI) \
+  case LI: if constexpr ((L << LI) <= kMaxPoints) { hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI>), grid, block, lds, s, a); return hipGetLastError(); } break;
+    FC_LI(1) FC_LI(2) FC_LI(3) FC_LI(4) FC_LI(5) FC_LI(6) FC_LI(7) FC_LI(8)
+#undef FC_LI
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int IO, int SZ>
+hipError_t launch_size(int cls, const LaunchArgs& a, int aux, size_t lds, hipStream_t s, dim3 grid) {
+  dim3 block(kThreads);
+  if (cls == 0) return launch_pruned<IO, SZ>(a, aux, lds, s, grid);
+  if (cls == 1) {
+    hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ>), grid, block, lds, s, a, aux);
+  } else {
+    hipLaunchKernelGGL((fc_rx_kernel<IO, SZ>), grid, block, lds, s, a, aux);
+  }
+  return hipGetLastError();
+}
+
+template <int IO>
+hipError_t launch_io(int cls, int size, const LaunchArgs& a, int aux, size_t lds, hipStream_t s) {
+  if (a.n_task <= 0) return hipSuccess;
+  dim3 grid(cls == 2 ? ((a.n_task + 7) & ~7) : a.n_task);
+  switch (size) {
+#define FC_SZ(SZ) case SZ: return launch_size<IO, SZ>(cls, a, aux, lds, s, grid);
+    FC_SZ(16) FC_SZ(32) FC_SZ(64) FC_SZ(128) FC_SZ(256) FC_SZ(512) FC_SZ(1024) FC_SZ(2048) FC_SZ(4096)
+#undef FC_SZ
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int IO>
+hipError_t launch_zero_io(void* out, int64_t n, hipStream_t s) {
+  int64_t blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(fc_zero_kernel<IO>, dim3((unsigned)blocks), dim3(kThreads), 0, s, out, n);
+  return hipGetLastError();
+}
+
+template <int IO, int L>
+hipError_t lds_limit_pruned(size_t bytes) {
+  hipError_t e = hipSuccess;
+#define FC_LI(LI)                                                                                   \
+  if constexpr ((L << LI) <= kMaxPoints) {                                                          \
+    hipError_t r = hipFuncSetAttribute((const void*)fc_tx_pruned_kernel<IO, L, LI>,                 \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);     \
+    if (r != hipSuccess) e = r;                                                                     \
+  }
+  FC_LI(1) FC_LI(2) FC_LI(3) FC_LI(4) FC_LI(5) FC_LI(6) FC_LI(7) FC_LI(8)
+#undef FC_LI
+  return e;
+}
+
+template <int IO>
+hipError_t lds_limits_io(size_t bytes) {
+  hipError_t e = hipSuccess;
+#define FC_SZ(SZ)                                                                                   \
+  {                                                                                                 \
+    hipError_t r1 = lds_limit_pruned<IO, SZ>(bytes);                                                \
+    hipError_t r2 = hipFuncSetAttribute((const void*)fc_tx_full_kernel<IO, SZ>,                     \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
+    hipError_t r3 = hipFuncSetAttribute((const void*)fc_rx_kernel<IO, SZ>,                          \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
+    if (r1 != hipSuccess) e = r1;                                                                   \
+    if (r2 != hipSuccess) e = r2;                                                                   \
+    if (r3 != hipSuccess) e = r3;                                                                   \
+  }
+  FC_SZ(16) FC_SZ(32) FC_SZ(64) FC_SZ(128) FC_SZ(256) FC_SZ(512) FC_SZ(1024) FC_SZ(2048) FC_SZ(4096)
+#undef FC_SZ
+  return e;
+}
+
+}  // namespace fcx

@@ -12,6 +12,10 @@ constexpr int kTwiddleN = 4096;      // global twiddle table: exp(-j 2 pi k / 40
 
 enum IoType : int32_t { IO_C64 = 0, IO_F16 = 1, IO_BF16 = 2 };
 
+// LDS slots of a transform buffer of n points (one pad slot per 32, see
+// the device code's pad()).
+constexpr int lds_elems(int n) { return n + (n >> 5); }
+
 struct Cf {   // complex float with the same layout as HIP's float2
   float x, y;
 };
@@ -22,7 +26,7 @@ struct SbDesc {
   int32_t c;              // centre bin c_m (signed)
   int32_t q0;             // (c_m - L_m/2) mod N: long bin of shifted index p = 0
   int32_t w_off;          // offset of this subband's weights in the weight table
-  int32_t pad0;
+  int32_t wave;           // RX: wave (0..3) running this subband's short IFFT, -1: whole workgroup
   int64_t lo_off;         // element offset of the subband's low-rate data for this op
   int64_t lo_len;         // number of low-rate samples for this op
 };

@@ -23,8 +23,7 @@
 #include "fc_internal.h"
 
 namespace fcx {
-hipError_t launch_tx(const LaunchArgs& a, int lmax, size_t lds, hipStream_t s);
-hipError_t launch_rx(const LaunchArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_kernel(int cls, int size, const LaunchArgs& a, int aux, size_t lds, hipStream_t s);
 hipError_t launch_zero(void* out, int64_t n, int io, hipStream_t s);
 hipError_t set_lds_limits(size_t bytes);
 }  // namespace fcx
@@ -83,8 +82,9 @@ struct Op {
   std::vector<BlockDesc> blk;
   std::vector<BlockSb> bsb;
   std::vector<TaskDesc> task;
-  struct Phase { int kind; int first, count; size_t lds; int lmax; int64_t zero_n; };
-  // kind: 0 = TX kernel, 1 = RX kernel, 2 = zero the output buffer
+  // One kernel launch. kind: 0 = FC kernel of class cls (0 TX pruned, 1 TX
+  // full, 2 RX) and transform size `size`; 2 = zero the output buffer.
+  struct Phase { int kind; int first, count; size_t lds; int aux; int64_t zero_n; int cls, size; };
   std::vector<Phase> phases;
   // device copies
   SbDesc* d_sb = nullptr; GroupDesc* d_grp = nullptr; BlockDesc* d_blk = nullptr;
@@ -248,13 +248,29 @@ void build_op(fc_plan* P, int kind) {
       d.L = s.L; d.logL = s.logL; d.c = s.d.center_bin;
       d.q0 = (int)imod((int64_t)s.d.center_bin - s.L / 2, s.N);
       d.w_off = P->w_off[m];
+      d.wave = -1;
       d.lo_off = op.lo_off[m]; d.lo_len = op.lo_off[m + 1] - op.lo_off[m];
       sb_index[m] = (int)op.sb.size();
       op.sb.push_back(d);
     }
+    // RX: spread the one-wave short IFFTs (L <= 1024) over the four waves,
+    // largest first onto the least loaded wave
+    if (kind != 0) {
+      std::vector<int> idx;
+      for (int i = 0; i < gd.n_sb; ++i)
+        if (op.sb[gd.sb_first + i].L <= 1024) idx.push_back(gd.sb_first + i);
+      std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return op.sb[x].L > op.sb[y].L; });
+      double load[4] = {0, 0, 0, 0};
+      for (int i : idx) {
+        int w = (int)(std::min_element(load, load + 4) - load);
+        op.sb[i].wave = w;
+        load[w] += (double)op.sb[i].L * (op.sb[i].logL + 1);
+      }
+    }
   }
-  // blocks and tasks
-  struct PhaseTasks { std::vector<TaskDesc> t; int lmax = 0; size_t lds = 0; };
+  // blocks and tasks; tasks are collected per launch phase and kernel class
+  struct ClassTasks { std::vector<TaskDesc> t; size_t lds = 0; int aux = 0; };
+  struct PhaseTasks { std::map<std::tuple<int, int, int>, ClassTasks> cls; };
   std::map<int, PhaseTasks> tx_phase;        // TX: by group rank within the stream
   PhaseTasks rx_all, rx_even, rx_odd;
   bool any_acc_tx = false, any_ola_rx = false;
@@ -354,12 +370,18 @@ void build_op(fc_plan* P, int kind) {
             if (b1 == nblk) { t.z1_lo = Bl.t0 + Bl.hhi; t.z1_hi = span_hi; }
           }
         }
-        PhaseTasks& ph = tx_phase[G.rank];
-        ph.t.push_back(t);
-        ph.lmax = std::max(ph.lmax, lmax);
         const GroupDesc& gd = op.grp[g];
-        const size_t lds = gd.prune ? (size_t)(N + N / 2) * 8 : (size_t)(N + lmax + N / 2) * 8;
-        ph.lds = std::max(ph.lds, lds);
+        const std::tuple<int, int, int> key =
+            gd.prune ? std::make_tuple(0, s0.L, ilog2(s0.I)) : std::make_tuple(1, N, 0);
+        ClassTasks& ct = tx_phase[G.rank].cls[key];
+        ct.t.push_back(t);
+        if (gd.prune) {
+          ct.aux = ilog2(s0.I);
+          ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + N / 2) * 8);
+        } else {
+          ct.aux = std::max(ct.aux, lmax);
+          ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + lds_elems(ct.aux) + N / 2) * 8);
+        }
       }
     } else {
       // --- RX tasks: one block each ---
@@ -370,40 +392,54 @@ void build_op(fc_plan* P, int kind) {
         t.group = (int)g; t.blk_first = first_blk + b; t.blk_count = 1;
         t.accumulate = acc ? 1 : 0;
         PhaseTasks& ph = acc ? ((b & 1) ? rx_odd : rx_even) : rx_all;
-        ph.t.push_back(t);
-        ph.lmax = std::max(ph.lmax, lmax);
-        ph.lds = std::max(ph.lds, (size_t)(N + lmax) * 8);
+        ClassTasks& ct = ph.cls[std::make_tuple(2, N, 0)];
+        ct.t.push_back(t);
+        int wmax = 0, lbig = 0;
+        for (int m : G.subs) {
+          const int L = P->subs[m].L;
+          if (L <= 1024) wmax = std::max(wmax, L); else lbig = std::max(lbig, L);
+        }
+        ct.aux = std::max(ct.aux, wmax);
+        ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + std::max(4 * lds_elems(ct.aux), lds_elems(lbig))) * 8);
       }
     }
   }
-  auto emit = [&](int kindk, PhaseTasks& ph) {
-    if (ph.t.empty()) return;
-    // heavier tasks first: the dispatcher hands workgroups out in index order
-    std::stable_sort(ph.t.begin(), ph.t.end(), [&](const TaskDesc& a, const TaskDesc& b) {
-      auto cost = [&](const TaskDesc& t) { return (int64_t)op.grp[t.group].N * t.blk_count; };
-      return cost(a) > cost(b);
+  auto emit = [&](PhaseTasks& ph, bool sort_cost) {
+    // largest transforms first (several launches of one phase are independent)
+    std::vector<std::pair<std::tuple<int, int, int>, ClassTasks*>> order;
+    for (auto& kv : ph.cls) order.push_back({kv.first, &kv.second});
+    // largest transforms first: long size = size << log2 I for pruned classes
+    auto work = [](const std::tuple<int, int, int>& k) {
+      return std::get<0>(k) == 0 ? std::get<1>(k) << std::get<2>(k) : std::get<1>(k);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](const auto& a, const auto& b) {
+      return work(a.first) > work(b.first);
     });
-    Op::Phase p{kindk, (int)op.task.size(), (int)ph.t.size(), ph.lds, ph.lmax, 0};
-    op.task.insert(op.task.end(), ph.t.begin(), ph.t.end());
-    op.phases.push_back(p);
+    for (auto& kv : order) {
+      ClassTasks& ct = *kv.second;
+      if (ct.t.empty()) continue;
+      if (sort_cost) {
+        // heavier tasks first: the dispatcher hands workgroups out in index order
+        std::stable_sort(ct.t.begin(), ct.t.end(), [&](const TaskDesc& a, const TaskDesc& b) {
+          auto cost = [&](const TaskDesc& t) { return (int64_t)op.grp[t.group].N * t.blk_count; };
+          return cost(a) > cost(b);
+        });
+      }
+      Op::Phase p{0, (int)op.task.size(), (int)ct.t.size(), ct.lds, ct.aux, 0, std::get<0>(kv.first),
+                  std::get<1>(kv.first)};
+      op.task.insert(op.task.end(), ct.t.begin(), ct.t.end());
+      op.phases.push_back(p);
+    }
   };
   if (kind == 0) {
-    if (any_acc_tx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, P->hi_off.back()});
-    for (auto& kv : tx_phase) emit(0, kv.second);
+    if (any_acc_tx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, P->hi_off.back(), 0, 0});
+    for (auto& kv : tx_phase) emit(kv.second, true);
   } else {
-    if (any_ola_rx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, op.lo_off.back()});
+    if (any_ola_rx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, op.lo_off.back(), 0, 0});
     // RX tasks keep block order (neighbouring blocks share input in L2)
-    if (!rx_all.t.empty()) {
-      Op::Phase p{1, (int)op.task.size(), (int)rx_all.t.size(), rx_all.lds, rx_all.lmax, 0};
-      op.task.insert(op.task.end(), rx_all.t.begin(), rx_all.t.end());
-      op.phases.push_back(p);
-    }
-    for (PhaseTasks* ph : {&rx_even, &rx_odd}) {
-      if (ph->t.empty()) continue;
-      Op::Phase p{1, (int)op.task.size(), (int)ph->t.size(), ph->lds, ph->lmax, 0};
-      op.task.insert(op.task.end(), ph->t.begin(), ph->t.end());
-      op.phases.push_back(p);
-    }
+    emit(rx_all, false);
+    emit(rx_even, false);
+    emit(rx_odd, false);
   }
 }
 
@@ -441,7 +477,7 @@ fc_status run_op(fc_plan* P, int kind, const void* in, void* out, hipStream_t st
       a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
       a.weights = P->d_w; a.twiddle = P->d_tw; a.counter = nullptr;
       a.in = in; a.out = out;
-      e = ph.kind == 0 ? launch_tx(a, ph.lmax, ph.lds, st) : launch_rx(a, ph.lds, st);
+      e = launch_kernel(ph.cls, ph.size, a, ph.aux, ph.lds, st);
     }
     if (e != hipSuccess) { result = FC_E_DEVICE; break; }
   }

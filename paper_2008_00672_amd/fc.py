@@ -128,6 +128,13 @@ class Plan:
 
     # ---------------------------------------------------------- queries --
     def layout(self, op=OP_TX):
+        cache = self.__dict__.setdefault("_layouts", {})
+        if op in cache:
+            return cache[op]
+        cache[op] = self._layout(op)
+        return cache[op]
+
+    def _layout(self, op):
         lo = (ctypes.c_int64 * (self.n_sb + 1))()
         hi = (ctypes.c_int64 * (self.n_streams + 1))()
         _check(lib().fc_plan_layout(self._h, op, lo, hi), "fc_plan_layout")

@@ -118,22 +118,6 @@ template <int DIR> struct Dft<16, DIR> {
   }
 };
 
-// ------------------------------------------------------------ pass plan ---
-constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
-constexpr int npass(int P) { return P <= 16 ? 1 : (P <= 256 ? 2 : 3); }
-constexpr int radix_of(int P, int s) {
-  // 2..16: one pass; 32..256: two; 512..4096: three
-  return P <= 16 ? P
-       : P == 32 ? (s == 0 ? 8 : 4)
-       : P == 64 ? 8
-       : P == 128 ? (s == 0 ? 16 : 8)
-       : P == 256 ? 16
-       : P == 512 ? 8
-       : P == 1024 ? (s < 2 ? 16 : 4)
-       : P == 2048 ? (s < 2 ? 16 : 8)
-       : 16;
-}
-
 // LDS layout of the transform buffers between passes: one pad slot after
 // every 32 elements, so the strided butterfly writes of the early passes
 // spread over the banks. Buffers of n elements take lds_elems(n) slots.
@@ -150,12 +134,100 @@ __device__ __forceinline__ void group_sync() {
   if constexpr (NT == kThreads) __syncthreads(); else wave_sync();
 }
 
+template <int R> struct TwB {
+  float4 v[R >= 8 ? 2 : 1];
+};
+
+template <int NT, int P, int LOGBT, int S, int MAXIT, int R>
+__device__ __forceinline__ void twb_load(TwB<R> (&t)[MAXIT], const float2* __restrict__ twb, int tid) {
+  constexpr int NS = ns_of(P, S);
+  constexpr int TOTAL = (P / R) << LOGBT;
+  const float4* base = reinterpret_cast<const float4*>(twb + twb_off(P, S));
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it) {
+    const int g = tid + it * NT;
+    if (TOTAL % NT == 0 || g < TOTAL) {
+      const int k = (g >> LOGBT) & (NS - 1);
+      t[it].v[0] = base[2 * k];
+      if constexpr (R >= 8) t[it].v[1] = base[2 * k + 1];
+    }
+  }
+}
+
+template <int DIR>
+__device__ __forceinline__ float2 twc(float a, float b) { return make_float2(a, DIR > 0 ? -b : b); }
+
+// v[r] *= w^r for r = 1..R-1 (w^r from the four bases; DIR > 0 conjugates).
+template <int R, int DIR>
+__device__ __forceinline__ void apply_twiddles(float2* v, const TwB<R>& t) {
+  const float2 w1 = twc<DIR>(t.v[0].x, t.v[0].y);
+  if constexpr (R == 2) {
+    v[1] = cmul(v[1], w1);
+  } else {
+    const float2 w2 = twc<DIR>(t.v[0].z, t.v[0].w);
+    const float2 w3 = cmul(w1, w2);
+    v[1] = cmul(v[1], w1);
+    v[2] = cmul(v[2], w2);
+    v[3] = cmul(v[3], w3);
+    if constexpr (R >= 8) {
+      const float2 w4 = twc<DIR>(t.v[1].x, t.v[1].y);
+      const float2 w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
+      v[4] = cmul(v[4], w4);
+      v[5] = cmul(v[5], w5);
+      v[6] = cmul(v[6], w6);
+      v[7] = cmul(v[7], w7);
+      if constexpr (R == 16) {
+        const float2 w8 = twc<DIR>(t.v[1].z, t.v[1].w);
+        v[8] = cmul(v[8], w8);
+        v[9] = cmul(v[9], cmul(w1, w8));
+        v[10] = cmul(v[10], cmul(w2, w8));
+        v[11] = cmul(v[11], cmul(w3, w8));
+        v[12] = cmul(v[12], cmul(w4, w8));
+        v[13] = cmul(v[13], cmul(w5, w8));
+        v[14] = cmul(v[14], cmul(w6, w8));
+        v[15] = cmul(v[15], cmul(w7, w8));
+      }
+    }
+  }
+}
+
+// Slot s of the first pass: element index i and transform b it loads.
+template <int NT, int P, int LOGBT>
+__device__ __forceinline__ bool first_pos(int s, int tid, int& i, int& b) {
+  constexpr int R = radix_of(P, 0);
+  constexpr int NB = P / R;
+  constexpr int TOTAL = NB << LOGBT;
+  const int it = s / R, r = s % R;
+  const int g = tid + it * NT;
+  if (g >= TOTAL) return false;
+  b = g & ((1 << LOGBT) - 1);
+  i = (g >> LOGBT) + r * NB;
+  return true;
+}
+
+// Output position of register slot s of the last pass (-1: slot unused).
+template <int NT, int P, int LOGBT>
+__device__ __forceinline__ int last_pos(int s, int tid) {
+  constexpr int R = radix_of(P, npass(P) - 1);
+  constexpr int NB = P / R;
+  constexpr int TOTAL = NB << LOGBT;
+  const int it = s / R, r = s % R;
+  const int g = tid + it * NT;
+  if (g >= TOTAL) return -1;
+  const int b = g & ((1 << LOGBT) - 1), j = g >> LOGBT;
+  return ((j + r * NB) << LOGBT) + b;
+}
+
+template <int P, int R, int LOGBT, int NT>
+constexpr int maxit() { return (((P / R) << LOGBT) + NT - 1) / NT; }
+
 // One Stockham pass over P-point transforms, 2^LOGBT of them interleaved
 // (element i of transform b at index i * 2^LOGBT + b), run by NT threads.
-// NS is the product of the radices of the previous passes.
+// NS is the product of the radices of the previous passes. The first pass
+// reads through load(slot, i, b); the last hands results to store(slot, t, v).
 template <int NT, int P, int LOGBT, int R, int NS, int DIR, bool FIRST, bool LAST, class Load, class Store>
 __device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load& load, Store& store,
-                                         const float2* __restrict__ tw) {
+                                         const TwB<R>* tb) {
   constexpr int NB = P / R;
   constexpr int BT = 1 << LOGBT;
   constexpr int TOTAL = NB * BT;
@@ -170,7 +242,7 @@ __device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (FIRST)
-          v[it][r] = load(j + r * NB, b);
+          v[it][r] = load(it * R + r, j + r * NB, b);
         else
           v[it][r] = buf[pad(((j + r * NB) << LOGBT) + b)];
       }
@@ -183,16 +255,7 @@ __device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load
     if (TOTAL % NT == 0 || g < TOTAL) {
       const int b = g & (BT - 1), j = g >> LOGBT;
       const int k = j & (NS - 1);
-      if constexpr (!FIRST) {
-        constexpr int STRIDE = kTwiddleN / (NS * R);
-        const int ks = k * STRIDE;
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float2 w = tw[ks * r];
-          if (DIR > 0) w.y = -w.y;
-          v[it][r] = cmul(v[it][r], w);
-        }
-      }
+      if constexpr (!FIRST) apply_twiddles<R, DIR>(v[it], tb[it]);
       Dft<R, DIR>::run(v[it]);
       if constexpr (LAST) {
 #pragma unroll
@@ -210,28 +273,37 @@ __device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load
 // Whole transform: DIR = -1 forward DFT, +1 unnormalised inverse, of 2^LOGBT
 // interleaved P-point transforms. The caller provides a barrier before the
 // call when `buf`, or what `load` reads, was written by other threads.
+// load.prefetch / store.prefetch are called first, so functors can start
+// their own global loads (weights, twiddles) before the passes run.
 template <int NT, int P, int LOGBT, int DIR, class Load, class Store>
 __device__ __forceinline__ void fft_run(float2* buf, int tid, Load& load, Store& store,
-                                        const float2* __restrict__ tw) {
+                                        const float2* __restrict__ twb) {
   constexpr int NP = npass(P);
   constexpr int R0 = radix_of(P, 0), R1 = radix_of(P, 1), R2 = radix_of(P, 2);
-  fft_pass<NT, P, LOGBT, R0, 1, DIR, true, NP == 1>(buf, tid, load, store, tw);
-  if constexpr (NP >= 2) fft_pass<NT, P, LOGBT, R1, R0, DIR, false, NP == 2>(buf, tid, load, store, tw);
-  if constexpr (NP >= 3) fft_pass<NT, P, LOGBT, R2, R0 * R1, DIR, false, true>(buf, tid, load, store, tw);
+  static_assert(NT == kThreads || P <= 1024, "one wave holds at most 1024 points");
+  // All LDS and twiddle indices of a pass depend only on the thread, so the
+  // compiler would compute every transform's indices (and twiddle loads) once
+  // outside the block loops and keep them all live for the whole kernel. That
+  // costs far more occupancy than recomputing them costs ALU, so both the
+  // thread index and the table pointer are made opaque per transform.
+  asm volatile("" : "+v"(tid));
+  asm volatile("" : "+s"(twb));
+  constexpr int M1 = maxit<P, R1, LOGBT, NT>(), M2 = maxit<P, R2, LOGBT, NT>();
+  TwB<R1> t1[M1];
+  TwB<R2> t2[M2];
+  if constexpr (NP >= 2) twb_load<NT, P, LOGBT, 1>(t1, twb, tid);
+  if constexpr (NP >= 3) twb_load<NT, P, LOGBT, 2>(t2, twb, tid);
+  load.prefetch(tid);
+  store.prefetch(tid);
+  fft_pass<NT, P, LOGBT, R0, 1, DIR, true, NP == 1>(buf, tid, load, store, (const TwB<R0>*)nullptr);
+  if constexpr (NP >= 2) fft_pass<NT, P, LOGBT, R1, R0, DIR, false, NP == 2>(buf, tid, load, store, t1);
+  if constexpr (NP >= 3) fft_pass<NT, P, LOGBT, R2, R0 * R1, DIR, false, true>(buf, tid, load, store, t2);
 }
 
-// Output position of register slot s of the last pass (-1: slot unused).
-template <int NT, int P, int LOGBT>
-__device__ __forceinline__ int last_pos(int s, int tid) {
-  constexpr int R = radix_of(P, npass(P) - 1);
-  constexpr int NB = P / R;
-  constexpr int TOTAL = NB << LOGBT;
-  const int it = s / R, r = s % R;
-  const int g = tid + it * NT;
-  if (g >= TOTAL) return -1;
-  const int b = g & ((1 << LOGBT) - 1), j = g >> LOGBT;
-  return ((j + r * NB) << LOGBT) + b;
-}
+// Functors without prefetch work derive from this.
+struct NoPrefetch {
+  __device__ __forceinline__ void prefetch(int) {}
+};
 
 // ------------------------------------------------------------------- I/O --
 // Interleaved I/Q storage; element pointers are formed once per block from the
@@ -278,44 +350,63 @@ __device__ __forceinline__ void put(typename Io<IO>::T* p, int i, float2 v, bool
 
 // ------------------------------------------------------------- functors ---
 // Low-rate segment: block sample i is x[i] inside [lo, hi), else 0.
-template <int IO> struct LoadSeg {
+template <int IO> struct LoadSeg : NoPrefetch {
   const typename Io<IO>::T* x; int lo, hi;
-  __device__ __forceinline__ float2 operator()(int i, int) const {
+  __device__ __forceinline__ float2 operator()(int, int i, int) const {
     return (i >= lo && i < hi) ? Io<IO>::ld(x, i) : make_float2(0.f, 0.f);
   }
 };
 
 // Natural-order LDS read (first pass reading an LDS spectrum).
-struct LoadLds {
+struct LoadLds : NoPrefetch {
   const float2* s;
-  __device__ __forceinline__ float2 operator()(int i, int) const { return s[i]; }
+  __device__ __forceinline__ float2 operator()(int, int i, int) const { return s[i]; }
 };
 
 // TX, pruned long IFFT: short-FFT bin u -> residue rho = (u + c) mod L of the
 // band, weighted by D[p] (p = (u + L/2) mod L, the fftshifted index) and the
-// block phase.
-template <int L> struct StoreBand {
+// block phase. The weights of this thread's output bins are fetched when the
+// transform starts.
+template <int NT, int L> struct StoreBand {
   float2* V; const float* D; float2 ph; int c;
-  __device__ __forceinline__ void operator()(int, int u, float2 v) const {
-    const int p = (u + (L >> 1)) & (L - 1);
-    V[(u + c) & (L - 1)] = cscale(cmul(v, ph), D[p]);
+  float d[16];
+  __device__ __forceinline__ void prefetch(int tid) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int u = last_pos<NT, L, 0>(s, tid);
+      if (u >= 0) d[s] = D[(u + (L >> 1)) & (L - 1)];
+    }
+  }
+  __device__ __forceinline__ void operator()(int slot, int u, float2 v) const {
+    V[(u + c) & (L - 1)] = cscale(cmul(v, ph), d[slot]);
   }
 };
 
 // TX, pruned long IFFT first pass: sub-transform b (output samples t = a*I + b)
 // of residue rho takes V[rho] * exp(+j 2 pi q b / N), q the band bin of rho.
-template <int L, int N> struct LoadPruned {
+// The twiddles depend only on the thread and the subband, so they are fetched
+// before the short FFT of the block runs.
+template <int NT, int L, int LOGI> struct LoadPruned {
+  static constexpr int N = L << LOGI;
   const float2* V; const float2* tw; int q0;
-  __device__ __forceinline__ float2 operator()(int rho, int b) const {
-    const int q = (q0 + ((rho - q0) & (L - 1))) & (N - 1);
-    float2 w = tw[((q * b) & (N - 1)) * (kTwiddleN / N)];
-    w.y = -w.y;
-    return cmul(V[rho], w);
+  float2 w[16];
+  __device__ __forceinline__ void prefetch(int tid) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      int rho, b;
+      if (first_pos<NT, L, LOGI>(s, tid, rho, b)) {
+        const int q = (q0 + ((rho - q0) & (L - 1))) & (N - 1);
+        w[s] = tw[((q * b) & (N - 1)) * (kTwiddleN / N)];
+      }
+    }
+  }
+  __device__ __forceinline__ float2 operator()(int slot, int rho, int) const {
+    return cmul(V[rho], make_float2(w[slot].x, -w[slot].y));
   }
 };
 
 // TX, full long IFFT: add the weighted band into the N-bin spectrum.
-template <int N> struct StoreAddLong {
+template <int N> struct StoreAddLong : NoPrefetch {
   float2* S; const float* D; float2 ph; int L, q0;
   __device__ __forceinline__ void operator()(int, int u, float2 v) const {
     const int p = (u + (L >> 1)) & (L - 1);
@@ -326,7 +417,7 @@ template <int N> struct StoreAddLong {
 
 // TX epilogue, phase 1 (inside the last pass): OLA carry-in for block samples
 // t < pth; results stay in registers until phase 2.
-struct TxEpi {
+struct TxEpi : NoPrefetch {
   const float2* pend; int pth;
   float2 val[16];
   __device__ __forceinline__ void operator()(int slot, int t, float2 v) {
@@ -336,31 +427,39 @@ struct TxEpi {
 };
 
 // RX: long-FFT result into the LDS spectrum (natural order).
-struct StoreLds {
+struct StoreLds : NoPrefetch {
   float2* s;
   __device__ __forceinline__ void operator()(int, int t, float2 v) const { s[t] = v; }
 };
 
 // High-rate segment with an input window [lo, hi).
-template <int IO> struct LoadHigh {
+template <int IO> struct LoadHigh : NoPrefetch {
   const typename Io<IO>::T* x; int lo, hi;
-  __device__ __forceinline__ float2 operator()(int i, int) const {
+  __device__ __forceinline__ float2 operator()(int, int i, int) const {
     return (i >= lo && i < hi) ? Io<IO>::ld(x, i) : make_float2(0.f, 0.f);
   }
 };
 
 // RX short IFFT first pass: bin u of the subband (inverse shift) gathers long
 // bin q = (q0 + p) mod N, p = (u + L/2) mod L, weighted by D[p] and conj phase.
-template <int L, int N> struct LoadGather {
+template <int NT, int L, int N> struct LoadGather {
   const float2* S; const float* D; float2 ph; int q0;
-  __device__ __forceinline__ float2 operator()(int u, int) const {
+  float d[16];
+  __device__ __forceinline__ void prefetch(int tid) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      int u, b;
+      if (first_pos<NT, L, 0>(s, tid, u, b)) d[s] = D[(u + (L >> 1)) & (L - 1)];
+    }
+  }
+  __device__ __forceinline__ float2 operator()(int slot, int u, int) const {
     const int p = (u + (L >> 1)) & (L - 1);
-    return cscale(cmul(S[(q0 + p) & (N - 1)], ph), D[p]);
+    return cscale(cmul(S[(q0 + p) & (N - 1)], ph), d[slot]);
   }
 };
 
 // RX output: keep window [lo, hi) of the low-rate block.
-template <int IO> struct StoreLow {
+template <int IO> struct StoreLow : NoPrefetch {
   typename Io<IO>::T* out; int lo, hi; bool acc;
   __device__ __forceinline__ void operator()(int, int i, float2 v) const {
     if (i >= lo && i < hi) put<IO>(out, i, v, acc);
@@ -430,6 +529,7 @@ __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
   float2* pend = smem + lds_elems(N);       // OLA carry, up to N/2 points
   const float* D = a.weights + S.w_off;
   const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
+  const float2* twb = reinterpret_cast<const float2*>(a.twpass);
   const int tid = threadIdx.x;
   int64_t prev_end = INT64_MIN;
   for (int bi = 0; bi < T.blk_count; ++bi) {
@@ -438,19 +538,27 @@ __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
     const int64_t next_start =
         (T.ola && bi + 1 < T.blk_count) ? a.blk[T.blk_first + bi + 1].t0 : INT64_MAX;
     const TxWin w = tx_window(B, T, prev_end, next_start, N);
-    LoadSeg<IO> ld{at<IO>(a.in, Z.x0), Z.lo, Z.hi};
-    StoreBand<L> sb{buf, D, make_float2(Z.ph.x, Z.ph.y), S.c};
+    LoadSeg<IO> ld;
+    ld.x = at<IO>(a.in, Z.x0); ld.lo = Z.lo; ld.hi = Z.hi;
+    LoadPruned<kThreads, L, LOGI> lp;
+    lp.V = buf; lp.tw = tw; lp.q0 = S.q0;
+    lp.prefetch(tid);
     __syncthreads();
     if constexpr (L <= 1024) {
-      if (tid < 64) fft_run<64, L, 0, -1>(buf, tid, ld, sb, tw);
+      if (tid < 64) {
+        StoreBand<64, L> sb;
+        sb.V = buf; sb.D = D; sb.ph = make_float2(Z.ph.x, Z.ph.y); sb.c = S.c;
+        fft_run<64, L, 0, -1>(buf, tid, ld, sb, twb);
+      }
     } else {
-      fft_run<kThreads, L, 0, -1>(buf, tid, ld, sb, tw);
+      StoreBand<kThreads, L> sb;
+      sb.V = buf; sb.D = D; sb.ph = make_float2(Z.ph.x, Z.ph.y); sb.c = S.c;
+      fft_run<kThreads, L, 0, -1>(buf, tid, ld, sb, twb);
     }
     __syncthreads();
-    LoadPruned<L, N> lp{buf, tw, S.q0};
     TxEpi ep;
     ep.pend = pend; ep.pth = w.pth;
-    fft_run<kThreads, L, LOGI, +1>(buf, tid, lp, ep, tw);
+    fft_run<kThreads, L, LOGI, +1>(buf, tid, lp, ep, twb);
     __syncthreads();
     tx_epilogue<IO, kThreads, L, LOGI>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0);
     prev_end = T.ola ? B.t0 + N : INT64_MIN;
@@ -473,7 +581,7 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
   float2* S = smem;                                  // N-bin spectrum, then the in-place IFFT
   float2* bs = smem + lds_elems(NL);                 // short FFT scratch
   float2* pend = bs + lds_elems(lmax);               // OLA carry (N/2)
-  const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
+  const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const int tid = threadIdx.x;
   int64_t prev_end = INT64_MIN;
   for (int bi = 0; bi < T.blk_count; ++bi) {
@@ -486,8 +594,10 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
     for (int m = 0; m < G.n_sb; ++m) {
       const SbDesc Sb = a.sb[G.sb_first + m];
       const BlockSb Z = a.bsb[B.bs + m];
-      LoadSeg<IO> ld{at<IO>(a.in, Z.x0), Z.lo, Z.hi};
-      StoreAddLong<NL> st{S, a.weights + Sb.w_off, make_float2(Z.ph.x, Z.ph.y), Sb.L, Sb.q0};
+      LoadSeg<IO> ld;
+      ld.x = at<IO>(a.in, Z.x0); ld.lo = Z.lo; ld.hi = Z.hi;
+      StoreAddLong<NL> st;
+      st.S = S; st.D = a.weights + Sb.w_off; st.ph = make_float2(Z.ph.x, Z.ph.y); st.L = Sb.L; st.q0 = Sb.q0;
       __syncthreads();
       switch (Sb.L) {
 #define FC_SHORT(LL) case LL: if constexpr (LL <= NL) fft_run<kThreads, LL, 0, -1>(bs, tid, ld, st, tw); break;
@@ -498,7 +608,8 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
       }
     }
     __syncthreads();
-    LoadLds ls{S};
+    LoadLds ls;
+    ls.s = S;
     TxEpi ep;
     ep.pend = pend; ep.pth = w.pth;
     fft_run<kThreads, NL, 0, +1>(S, tid, ls, ep, tw);
@@ -528,11 +639,13 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   float2* ws = smem + lds_elems(NL) + wave * lds_elems(wmax);   // this wave's scratch
   float2* bs = smem + lds_elems(NL);                       // workgroup scratch (long subbands)
-  const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
+  const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   for (int bi = 0; bi < T.blk_count; ++bi) {
     const BlockDesc B = a.blk[T.blk_first + bi];
-    LoadHigh<IO> lh{at<IO>(a.in, B.t0), B.hlo, B.hhi};
-    StoreLds sl{S};
+    LoadHigh<IO> lh;
+    lh.x = at<IO>(a.in, B.t0); lh.lo = B.hlo; lh.hi = B.hhi;
+    StoreLds sl;
+    sl.s = S;
     __syncthreads();
     fft_run<kThreads, NL, 0, -1>(S, tid, lh, sl, tw);
     __syncthreads();
@@ -544,13 +657,15 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax)
       const BlockSb Z = a.bsb[B.bs + m];
       const float* D = a.weights + Sb.w_off;
       const float2 ph = make_float2(Z.ph.x, Z.ph.y);
-      StoreLow<IO> so{at<IO>(a.out, Z.x0), Z.lo, Z.hi, T.accumulate != 0};
+      StoreLow<IO> so;
+      so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
       wave_sync();
       switch (Sb.L) {
 #define FC_SHORT(LL)                                                   \
   case LL:                                                             \
     if constexpr (LL <= NL) {                                          \
-      LoadGather<LL, NL> lg{S, D, ph, Sb.q0};                          \
+      LoadGather<64, LL, NL> lg;                                       \
+      lg.S = S; lg.D = D; lg.ph = ph; lg.q0 = Sb.q0;                   \
       fft_run<64, LL, 0, +1>(ws, lane, lg, so, tw);                    \
     }                                                                  \
     break;
@@ -566,13 +681,15 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax)
         const BlockSb Z = a.bsb[B.bs + m];
         const float* D = a.weights + Sb.w_off;
         const float2 ph = make_float2(Z.ph.x, Z.ph.y);
-        StoreLow<IO> so{at<IO>(a.out, Z.x0), Z.lo, Z.hi, T.accumulate != 0};
+        StoreLow<IO> so;
+        so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
         __syncthreads();
         switch (Sb.L) {
 #define FC_SHORT(LL)                                                   \
   case LL:                                                             \
     if constexpr (LL <= NL && LL > 1024) {                             \
-      LoadGather<LL, NL> lg{S, D, ph, Sb.q0};                          \
+      LoadGather<kThreads, LL, NL> lg;                                 \
+      lg.S = S; lg.D = D; lg.ph = ph; lg.q0 = Sb.q0;                   \
       fft_run<kThreads, LL, 0, +1>(bs, tid, lg, so, tw);               \
     }                                                                  \
     break;

@@ -20,6 +20,38 @@ struct Cf {   // complex float with the same layout as HIP's float2
   float x, y;
 };
 
+// ------------------------------------------------------------ pass plan ---
+constexpr int npass(int P) { return P <= 16 ? 1 : (P <= 256 ? 2 : 3); }
+constexpr int radix_of(int P, int s) {
+  // 2..16: one pass; 32..256: two; 512..4096: three
+  return P <= 16 ? P
+       : P == 32 ? (s == 0 ? 8 : 4)
+       : P == 64 ? 8
+       : P == 128 ? (s == 0 ? 16 : 8)
+       : P == 256 ? 16
+       : P == 512 ? 8
+       : P == 1024 ? (s < 2 ? 16 : 4)
+       : P == 2048 ? (s < 2 ? 16 : 8)
+       : 16;
+}
+
+// Per-pass twiddle bases. A non-first pass with NS preceding points and radix
+// R needs w^r = exp(DIR j 2 pi k r / (NS R)) for r = 1..R-1 at its butterfly
+// index k. The table holds, per (P, pass, k), the four bases w^1, w^2, w^4,
+// w^8 (32 bytes, FP64-computed on the host); the other powers are products of
+// at most three bases, so each butterfly loads two 16-byte vectors instead of
+// R-1 separate twiddles, and all passes' bases are fetched when a transform
+// starts, off the pass-to-pass critical path.
+constexpr int ns_of(int P, int s) { return s == 0 ? 1 : (s == 1 ? radix_of(P, 0) : radix_of(P, 0) * radix_of(P, 1)); }
+constexpr int twb_size(int P, int s) { return (s >= 1 && s < npass(P)) ? 4 * ns_of(P, s) : 0; }
+constexpr int twb_off(int P, int s) {
+  int off = 0;
+  for (int q = 2; q < P; q <<= 1) off += twb_size(q, 1) + twb_size(q, 2);
+  for (int t = 1; t < s; ++t) off += twb_size(P, t);
+  return off;
+}
+constexpr int twb_total() { return twb_off(2 * kMaxPoints, 1); }
+
 // One subband, shared by all operations.
 struct SbDesc {
   int32_t L, logL;        // short transform length L_m
@@ -76,7 +108,8 @@ struct LaunchArgs {
   int32_t n_task;
   int32_t io;
   const float* weights;
-  const Cf* twiddle;
+  const Cf* twiddle;         // exp(-j 2 pi k / kTwiddleN), k < kTwiddleN
+  const Cf* twpass;          // per-pass twiddle bases (device code's twb_off layout)
   unsigned int* counter;     // work counter (reset by the preceding reset kernel)
   const void* in;
   void* out;

@@ -103,6 +103,7 @@ struct fc_plan {
   int w_total = 0;
   float* d_w = nullptr;
   Cf* d_tw = nullptr;
+  Cf* d_twp = nullptr;           // per-pass twiddle bases
   Op op[3];
 };
 
@@ -475,7 +476,7 @@ fc_status run_op(fc_plan* P, int kind, const void* in, void* out, hipStream_t st
       LaunchArgs a{};
       a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
       a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
-      a.weights = P->d_w; a.twiddle = P->d_tw; a.counter = nullptr;
+      a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.counter = nullptr;
       a.in = in; a.out = out;
       e = launch_kernel(ph.cls, ph.size, a, ph.aux, ph.lds, st);
     }
@@ -580,9 +581,26 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
     const double a = 2.0 * kPi * k / kTwiddleN;
     tw[k] = Cf{(float)std::cos(a), (float)-std::sin(a)};
   }
+  // per-pass bases w^1, w^2, w^4, w^8 of w = exp(-j 2 pi k / (NS R)) for every
+  // non-first pass of every transform size (layout: twb_off)
+  std::vector<Cf> twp(twb_total());
+  for (int Pn = 2; Pn <= kMaxPoints; Pn <<= 1) {
+    for (int sp = 1; sp < npass(Pn); ++sp) {
+      const int NS = ns_of(Pn, sp), R = radix_of(Pn, sp);
+      for (int k = 0; k < NS; ++k) {
+        const int e[4] = {1, 2, 4, 8};
+        for (int q = 0; q < 4; ++q) {
+          const int64_t num = imod((int64_t)k * e[q], (int64_t)NS * R);
+          const double a = 2.0 * kPi * (double)num / (double)(NS * R);
+          twp[twb_off(Pn, sp) + 4 * k + q] = Cf{(float)std::cos(a), (float)-std::sin(a)};
+        }
+      }
+    }
+  }
   std::vector<float> w(P->w_total);
   for (int m = 0; m < n_sb; ++m) std::copy(P->subs[m].w.begin(), P->subs[m].w.end(), w.begin() + P->w_off[m]);
   if (!st) st = upload(tw, &P->d_tw);
+  if (!st) st = upload(twp, &P->d_twp);
   if (!st) st = upload(w, &P->d_w);
   for (int k = 0; k < 3 && !st; ++k) st = upload_op(P->op[k]);
   size_t lds_max = 0;
@@ -604,6 +622,7 @@ void fc_plan_destroy(fc_plan* P) {
   for (int k = 0; k < 3; ++k) free_op(P->op[k]);
   hipFree(P->d_w);
   hipFree(P->d_tw);
+  hipFree(P->d_twp);
   if (cur >= 0) hipSetDevice(cur);
   delete P;
 }

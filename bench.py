@@ -15,7 +15,6 @@ batching) is timed on the same work and reported beside it.
 Prints ONE JSON line. --gpus above 1 is refused (single-GPU build).
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -145,23 +144,18 @@ def rx_cost(sbs, bytes_per_sample):
     return (lo[-1] + hi[-1]) * bytes_per_sample, flops, int(hi[-1])
 
 
-def kernel_hash():
-    h = hashlib.sha256()
-    for f in ("fc_kernels.hip", "fc_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2008_00672_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
-
-
-def traffic(kernel, launches_per_step):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
+def traffic(op):
+    """HBM bytes per call of op from the committed rocprofv3 counter summary
+    (profiles/traffic_<op>.json), or None when the kernel sources changed
+    since the counters were taken."""
+    from paper_2008_00672_amd.profsum import kernel_hash
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % op)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_hash") != kernel_hash():
         return None
-    return d["bytes_per_launch"]
+    return round(d["bytes_per_launch"])
 
 
 # ------------------------------------------------------------ CPU leg ---
@@ -294,9 +288,9 @@ def main():
 
     # dominant kernel
     if tx_ms >= rx_ms:
-        dk, d_ms, d_bytes, d_flops = "fc_tx_kernel", tx_ms, tx_bytes, tx_flops
+        dk, d_ms, d_bytes, d_flops = "fc_tx", tx_ms, tx_bytes, tx_flops
     else:
-        dk, d_ms, d_bytes, d_flops = "fc_rx_kernel", rx_ms, rx_bytes, rx_flops
+        dk, d_ms, d_bytes, d_flops = "fc_rx", rx_ms, rx_bytes, rx_flops
     ai = d_flops / d_bytes
     ridge = ALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
     hbm_gbs = d_bytes / d_ms / 1e6
@@ -307,8 +301,9 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
-    roof["traffic"] = traffic(dk, 1)
-    roof["kernel"] = dk
+    roof["traffic"] = traffic(dk)
+    roof["kernel"] = dk + " (all class dispatches of one call)"
+    roof["algorithmic_bytes"] = int(d_bytes)
     roof["hbm_gbs"] = round(hbm_gbs, 1)
     roof["hbm_frac"] = round(hbm_gbs / HBM_PEAK_GBS, 4)
     roof["alu_frac_packed_peak"] = round(alu_tf / ALU_PEAK_PACKED_TFLOPS, 4)

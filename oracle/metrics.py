@@ -67,7 +67,7 @@ def oob_ratio_db(y, N, bands, guard=8):
 
 
 def complexity_per_symbol(n_long, subbands, alpha=2.0, beta=1.0):
-    """Real multiplications per data symbol, Sec. IV:
+    """Real multiplications per data symbol, Sec. V:
     C = (alpha mu(N) + sum_m [alpha beta mu(L_m) + 6 alpha N_tb,m + mu(L_OFDM,m)])
         / sum_m L_act,m, with subbands = [(L_m, L_OFDM_m, N_tb_m, L_act_m), ...].
     """

@@ -131,5 +131,5 @@ def mu_of_scs(scs_khz):
 
 
 def split_radix_mults(L):
-    """mu(L) = L log2 L - 3L + 4 real multiplications (Sec. IV)."""
+    """mu(L) = L log2 L - 3L + 4 real multiplications (Sec. V)."""
     return L * int(round(math.log2(L))) - 3 * L + 4

@@ -1,0 +1,91 @@
+"""Summaries of rocprofv3 output for this library's kernels.
+
+  python -m paper_2008_00672_amd.profsum stats <kernel_stats.csv> <out.md> "<command>"
+  python -m paper_2008_00672_amd.profsum traffic <op> <fetch.csv> <write.csv> \
+         <calib_fetch.csv> <calib_write.csv> <calls> <out.json> "<command>"
+
+`stats` turns a --kernel-trace --stats summary into a short markdown table.
+`traffic` sums FETCH_SIZE / WRITE_SIZE (KiB per dispatch) over the dispatches
+of one operation (all fc_tx_* kernels, or fc_rx_kernel), divides by the number
+of calls, and scales each counter by known-bytes / reading of a plain 256 MiB
+device copy profiled with the same counter. The result records a hash of the
+kernel sources so bench.py can tell whether it is still current.
+"""
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 256 << 20
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("fc_device.h", "fc_internal.h", "fc_kern_io.hip"):
+        h.update(open(os.path.join(HERE, "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _short(name):
+    n = name.replace("void fcx::", "").replace("fcx::", "")
+    return n.split("(")[0]
+
+
+def stats_md(path, out, command):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 kernel trace", "", "Command (repo root, MI355X):", "", "    " + command, "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    tx_avg = 0.0
+    for r in rows:
+        k = _short(r["Name"])
+        avg = float(r["AverageNs"]) / 1e3
+        if k.startswith("fc_tx_"):
+            tx_avg += avg
+        lines.append("| %s | %s | %.1f | %.2f | %.1f |" % (k, r["Calls"], avg, float(r["TotalDurationNs"]) / 1e6,
+                                                          float(r["Percentage"])))
+    lines += ["", "Sum of the fc_tx_* class averages (one TX call): %.1f us" % tx_avg, ""]
+    open(out, "w").write("\n".join(lines))
+
+
+def _dispatch_values(path, counter, select):
+    tot, n = 0.0, 0
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter or not select(_short(r["Kernel_Name"])):
+            continue
+        tot += float(r["Counter_Value"])
+        n += 1
+    return tot, n
+
+
+def _copy_reading(path, counter):
+    """Counter value of the 256 MiB copies: the median of the three largest
+    copy dispatches (the run makes exactly three such copies)."""
+    vals = sorted(float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                  if r["Counter_Name"] == counter and "copy" in r["Kernel_Name"].lower())
+    top = vals[-3:]
+    return top[len(top) // 2]
+
+
+def traffic(op, fetch, write, cfetch, cwrite, calls, out, command):
+    sel = (lambda k: k.startswith("fc_tx_")) if op == "fc_tx" else (lambda k: k.startswith("fc_rx_kernel"))
+    f_kib, nf = _dispatch_values(fetch, "FETCH_SIZE", sel)
+    w_kib, nw = _dispatch_values(write, "WRITE_SIZE", sel)
+    ff = COPY_BYTES / (_copy_reading(cfetch, "FETCH_SIZE") * 1024.0)
+    fw = COPY_BYTES / (_copy_reading(cwrite, "WRITE_SIZE") * 1024.0)
+    per_call = (f_kib * 1024.0 * ff + w_kib * 1024.0 * fw) / calls
+    d = {"op": op, "kernel_hash": kernel_hash(), "bytes_per_launch": per_call,
+         "fetch_kib_per_call": f_kib / calls, "write_kib_per_call": w_kib / calls,
+         "copy_factor_fetch": ff, "copy_factor_write": fw, "dispatches": [nf, nw], "calls": calls,
+         "command": command}
+    json.dump(d, open(out, "w"), indent=1)
+    return d
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats_md(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        print(traffic(sys.argv[2], *sys.argv[3:7], int(sys.argv[7]), sys.argv[8], sys.argv[9]))

@@ -300,9 +300,19 @@ __device__ __forceinline__ void fft_run(float2* buf, int tid, Load& load, Store&
   if constexpr (NP >= 3) fft_pass<NT, P, LOGBT, R2, R0 * R1, DIR, false, true>(buf, tid, load, store, t2);
 }
 
+template <int V> struct SizeC { static constexpr int value = V; };
+
 // Functors without prefetch work derive from this.
 struct NoPrefetch {
   __device__ __forceinline__ void prefetch(int) {}
+};
+
+// Uses a functor whose prefetch already ran (fft_run's prefetch call is a no-op).
+template <class F> struct NoPrefetchWrap {
+  F& f;
+  __device__ __forceinline__ void prefetch(int) {}
+  template <class... A>
+  __device__ __forceinline__ auto operator()(A... args) -> decltype(f(args...)) { return f(args...); }
 };
 
 // ------------------------------------------------------------------- I/O --
@@ -354,6 +364,32 @@ template <int IO> struct LoadSeg : NoPrefetch {
   const typename Io<IO>::T* x; int lo, hi;
   __device__ __forceinline__ float2 operator()(int, int i, int) const {
     return (i >= lo && i < hi) ? Io<IO>::ld(x, i) : make_float2(0.f, 0.f);
+  }
+};
+
+// Input segment whose first-pass samples were loaded ahead of time (raw
+// storage words in registers): issue() starts the loads, typically while the
+// previous block is still being transformed; operator() converts on use.
+template <int IO, int NT, int P> struct LoadAhead : NoPrefetch {
+  using T = typename Io<IO>::T;
+  T raw[16];
+  unsigned valid;
+  __device__ __forceinline__ void issue(const T* x, int lo, int hi, int tid) {
+    // keep the loads where they are issued: hoisted above the transform that
+    // precedes them they would only lengthen register live ranges
+    asm volatile("" : "+v"(tid) : : "memory");
+    valid = 0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      int i, b;
+      if (first_pos<NT, P, 0>(s, tid, i, b) && i >= lo && i < hi) {
+        raw[s] = x[i];
+        valid |= 1u << s;
+      }
+    }
+  }
+  __device__ __forceinline__ float2 operator()(int slot, int, int) const {
+    return (valid >> slot) & 1u ? Io<IO>::ld(raw, slot) : make_float2(0.f, 0.f);
   }
 };
 
@@ -515,6 +551,11 @@ __device__ __forceinline__ void zero_span(void* out, int64_t lo, int64_t hi) {
 template <int IO, int L, int LOGI>
 __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
   constexpr int N = L << LOGI;
+  // the short FFT runs on one wave when it fits (no workgroup barriers)
+  constexpr int NTS = L <= 1024 ? 64 : kThreads;
+  // fetching the first-pass twiddles before the short FFT keeps 32 more
+  // registers live through it; worth it only where occupancy does not drop
+  constexpr bool kEarlyTwiddles = N <= 2048;
   extern __shared__ float2 smem[];
   const int task = blockIdx.x;
   if (task >= a.n_task) return;
@@ -531,34 +572,42 @@ __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
   const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
   const float2* twb = reinterpret_cast<const float2*>(a.twpass);
   const int tid = threadIdx.x;
+  const bool short_wave = NTS == kThreads || tid < 64;
   int64_t prev_end = INT64_MIN;
+  LoadAhead<IO, NTS, L> ld;
+  {
+    const BlockSb Z0 = a.bsb[a.blk[T.blk_first].bs];
+    if (short_wave) ld.issue(at<IO>(a.in, Z0.x0), Z0.lo, Z0.hi, tid);
+  }
   for (int bi = 0; bi < T.blk_count; ++bi) {
     const BlockDesc B = a.blk[T.blk_first + bi];
     const BlockSb Z = a.bsb[B.bs];
     const int64_t next_start =
         (T.ola && bi + 1 < T.blk_count) ? a.blk[T.blk_first + bi + 1].t0 : INT64_MAX;
     const TxWin w = tx_window(B, T, prev_end, next_start, N);
-    LoadSeg<IO> ld;
-    ld.x = at<IO>(a.in, Z.x0); ld.lo = Z.lo; ld.hi = Z.hi;
     LoadPruned<kThreads, L, LOGI> lp;
     lp.V = buf; lp.tw = tw; lp.q0 = S.q0;
-    lp.prefetch(tid);
+    if constexpr (kEarlyTwiddles) lp.prefetch(tid);
     __syncthreads();
-    if constexpr (L <= 1024) {
-      if (tid < 64) {
-        StoreBand<64, L> sb;
-        sb.V = buf; sb.D = D; sb.ph = make_float2(Z.ph.x, Z.ph.y); sb.c = S.c;
-        fft_run<64, L, 0, -1>(buf, tid, ld, sb, twb);
-      }
-    } else {
-      StoreBand<kThreads, L> sb;
+    if (short_wave) {
+      StoreBand<NTS, L> sb;
       sb.V = buf; sb.D = D; sb.ph = make_float2(Z.ph.x, Z.ph.y); sb.c = S.c;
-      fft_run<kThreads, L, 0, -1>(buf, tid, ld, sb, twb);
+      fft_run<NTS, L, 0, -1>(buf, tid, ld, sb, twb);
+    }
+    // start loading the next block's input while this block's IFFT runs
+    if (bi + 1 < T.blk_count && short_wave) {
+      const BlockSb Zn = a.bsb[a.blk[T.blk_first + bi + 1].bs];
+      ld.issue(at<IO>(a.in, Zn.x0), Zn.lo, Zn.hi, tid);
     }
     __syncthreads();
     TxEpi ep;
     ep.pend = pend; ep.pth = w.pth;
-    fft_run<kThreads, L, LOGI, +1>(buf, tid, lp, ep, twb);
+    if constexpr (kEarlyTwiddles) {
+      NoPrefetchWrap<LoadPruned<kThreads, L, LOGI>> lpw{lp};
+      fft_run<kThreads, L, LOGI, +1>(buf, tid, lpw, ep, twb);
+    } else {
+      fft_run<kThreads, L, LOGI, +1>(buf, tid, lp, ep, twb);
+    }
     __syncthreads();
     tx_epilogue<IO, kThreads, L, LOGI>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0);
     prev_end = T.ola ? B.t0 + N : INT64_MIN;
@@ -566,7 +615,8 @@ __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
 }
 
 // Several subbands share the long IFFT: their weighted bands are added into
-// one N-bin spectrum, then a full N-point IFFT.
+// one N-bin spectrum, then a full N-point IFFT. Short FFTs are dispatched by
+// size in separate loops (one region per size keeps register use low).
 template <int IO, int NL>
 __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int lmax) {
   extern __shared__ float2 smem[];
@@ -591,22 +641,25 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
     const TxWin w = tx_window(B, T, prev_end, next_start, NL);
     __syncthreads();
     for (int i = tid; i < NL; i += kThreads) S[i] = make_float2(0.f, 0.f);
-    for (int m = 0; m < G.n_sb; ++m) {
-      const SbDesc Sb = a.sb[G.sb_first + m];
-      const BlockSb Z = a.bsb[B.bs + m];
-      LoadSeg<IO> ld;
-      ld.x = at<IO>(a.in, Z.x0); ld.lo = Z.lo; ld.hi = Z.hi;
-      StoreAddLong<NL> st;
-      st.S = S; st.D = a.weights + Sb.w_off; st.ph = make_float2(Z.ph.x, Z.ph.y); st.L = Sb.L; st.q0 = Sb.q0;
-      __syncthreads();
-      switch (Sb.L) {
-#define FC_SHORT(LL) case LL: if constexpr (LL <= NL) fft_run<kThreads, LL, 0, -1>(bs, tid, ld, st, tw); break;
-        FC_SHORT(16) FC_SHORT(32) FC_SHORT(64) FC_SHORT(128) FC_SHORT(256) FC_SHORT(512)
-        FC_SHORT(1024) FC_SHORT(2048) FC_SHORT(4096)
-#undef FC_SHORT
-        default: break;
+    auto run_size = [&](auto lc) {
+      constexpr int LL = decltype(lc)::value;
+      if constexpr (LL <= NL) {
+        for (int m = 0; m < G.n_sb; ++m) {
+          const SbDesc Sb = a.sb[G.sb_first + m];
+          if (Sb.L != LL) continue;
+          const BlockSb Z = a.bsb[B.bs + m];
+          LoadSeg<IO> ld;
+          ld.x = at<IO>(a.in, Z.x0); ld.lo = Z.lo; ld.hi = Z.hi;
+          StoreAddLong<NL> st;
+          st.S = S; st.D = a.weights + Sb.w_off; st.ph = make_float2(Z.ph.x, Z.ph.y); st.L = LL; st.q0 = Sb.q0;
+          __syncthreads();
+          fft_run<kThreads, LL, 0, -1>(bs, tid, ld, st, tw);
+        }
       }
-    }
+    };
+    run_size(SizeC<4096>()); run_size(SizeC<2048>()); run_size(SizeC<1024>()); run_size(SizeC<512>());
+    run_size(SizeC<256>()); run_size(SizeC<128>()); run_size(SizeC<64>()); run_size(SizeC<32>());
+    run_size(SizeC<16>());
     __syncthreads();
     LoadLds ls;
     ls.s = S;
@@ -620,15 +673,16 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
 }
 
 // ------------------------------------------------------------- RX tasks ---
-// One block per task: the long FFT on the whole workgroup, then every subband's
-// gather + short IFFT. Subbands with L <= 1024 run as one-wave transforms, the
-// wave chosen by the planner (balanced over the four waves); longer ones use
-// the whole workgroup afterwards.
+// A run of consecutive blocks per task. Per block: the long FFT on the whole
+// workgroup, then every subband's gather + short IFFT. Subbands with
+// L <= 1024 run as one-wave transforms on the wave the planner chose
+// (balanced over the four waves); longer ones use the whole workgroup. The
+// next block's input is loaded into registers while the subbands run.
 template <int IO, int NL>
 __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax) {
   extern __shared__ float2 smem[];
-  // consecutive tasks (blocks sharing half of their input) go to the same XCD:
-  // the dispatcher places workgroup i on XCD i mod 8
+  // consecutive tasks (runs sharing input at their boundary) go to the same
+  // XCD: the dispatcher places workgroup i on XCD i mod 8
   const int n = gridDim.x;
   int task = blockIdx.x;
   if ((n & 7) == 0) task = (blockIdx.x & 7) * (n >> 3) + (blockIdx.x >> 3);
@@ -640,64 +694,59 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax)
   float2* ws = smem + lds_elems(NL) + wave * lds_elems(wmax);   // this wave's scratch
   float2* bs = smem + lds_elems(NL);                       // workgroup scratch (long subbands)
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
+  LoadAhead<IO, kThreads, NL> lh;
+  {
+    const BlockDesc B0 = a.blk[T.blk_first];
+    lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
+  }
   for (int bi = 0; bi < T.blk_count; ++bi) {
     const BlockDesc B = a.blk[T.blk_first + bi];
-    LoadHigh<IO> lh;
-    lh.x = at<IO>(a.in, B.t0); lh.lo = B.hlo; lh.hi = B.hhi;
     StoreLds sl;
     sl.s = S;
     __syncthreads();
     fft_run<kThreads, NL, 0, -1>(S, tid, lh, sl, tw);
-    __syncthreads();
-    bool any_long = false;
-    for (int m = 0; m < G.n_sb; ++m) {
-      const SbDesc Sb = a.sb[G.sb_first + m];
-      if (Sb.wave < 0) { any_long = true; continue; }
-      if (Sb.wave != wave) continue;
-      const BlockSb Z = a.bsb[B.bs + m];
-      const float* D = a.weights + Sb.w_off;
-      const float2 ph = make_float2(Z.ph.x, Z.ph.y);
-      StoreLow<IO> so;
-      so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
-      wave_sync();
-      switch (Sb.L) {
-#define FC_SHORT(LL)                                                   \
-  case LL:                                                             \
-    if constexpr (LL <= NL) {                                          \
-      LoadGather<64, LL, NL> lg;                                       \
-      lg.S = S; lg.D = D; lg.ph = ph; lg.q0 = Sb.q0;                   \
-      fft_run<64, LL, 0, +1>(ws, lane, lg, so, tw);                    \
-    }                                                                  \
-    break;
-        FC_SHORT(16) FC_SHORT(32) FC_SHORT(64) FC_SHORT(128) FC_SHORT(256) FC_SHORT(512) FC_SHORT(1024)
-#undef FC_SHORT
-        default: break;
-      }
+    if (bi + 1 < T.blk_count) {
+      const BlockDesc Bn = a.blk[T.blk_first + bi + 1];
+      lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
     }
-    if (any_long) {
-      for (int m = 0; m < G.n_sb; ++m) {
-        const SbDesc Sb = a.sb[G.sb_first + m];
-        if (Sb.wave >= 0) continue;
-        const BlockSb Z = a.bsb[B.bs + m];
-        const float* D = a.weights + Sb.w_off;
-        const float2 ph = make_float2(Z.ph.x, Z.ph.y);
-        StoreLow<IO> so;
-        so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
-        __syncthreads();
-        switch (Sb.L) {
-#define FC_SHORT(LL)                                                   \
-  case LL:                                                             \
-    if constexpr (LL <= NL && LL > 1024) {                             \
-      LoadGather<kThreads, LL, NL> lg;                                 \
-      lg.S = S; lg.D = D; lg.ph = ph; lg.q0 = Sb.q0;                   \
-      fft_run<kThreads, LL, 0, +1>(bs, tid, lg, so, tw);               \
-    }                                                                  \
-    break;
-          FC_SHORT(2048) FC_SHORT(4096)
-#undef FC_SHORT
-          default: break;
+    __syncthreads();
+    auto run_wave = [&](auto lc) {
+      constexpr int LL = decltype(lc)::value;
+      if constexpr (LL <= NL) {
+        for (int m = 0; m < G.n_sb; ++m) {
+          const SbDesc Sb = a.sb[G.sb_first + m];
+          if (Sb.L != LL || Sb.wave != wave) continue;
+          const BlockSb Z = a.bsb[B.bs + m];
+          StoreLow<IO> so;
+          so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
+          LoadGather<64, LL, NL> lg;
+          lg.S = S; lg.D = a.weights + Sb.w_off; lg.ph = make_float2(Z.ph.x, Z.ph.y); lg.q0 = Sb.q0;
+          wave_sync();
+          fft_run<64, LL, 0, +1>(ws, lane, lg, so, tw);
         }
       }
+    };
+    run_wave(SizeC<1024>()); run_wave(SizeC<512>()); run_wave(SizeC<256>()); run_wave(SizeC<128>());
+    run_wave(SizeC<64>()); run_wave(SizeC<32>()); run_wave(SizeC<16>());
+    auto run_group = [&](auto lc) {
+      constexpr int LL = decltype(lc)::value;
+      if constexpr (LL <= NL) {
+        for (int m = 0; m < G.n_sb; ++m) {
+          const SbDesc Sb = a.sb[G.sb_first + m];
+          if (Sb.L != LL || Sb.wave >= 0) continue;
+          const BlockSb Z = a.bsb[B.bs + m];
+          StoreLow<IO> so;
+          so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
+          LoadGather<kThreads, LL, NL> lg;
+          lg.S = S; lg.D = a.weights + Sb.w_off; lg.ph = make_float2(Z.ph.x, Z.ph.y); lg.q0 = Sb.q0;
+          __syncthreads();
+          fft_run<kThreads, LL, 0, +1>(bs, tid, lg, so, tw);
+        }
+      }
+    };
+    if (G.n_long_sb > 0) {
+      run_group(SizeC<2048>());
+      run_group(SizeC<4096>());
     }
   }
 }

@@ -68,7 +68,7 @@ struct GroupDesc {
   int32_t N, logN;
   int32_t n_sb, sb_first;    // subbands [sb_first, sb_first + n_sb) of the op's table
   int32_t prune;             // TX: 1 when the long IFFT is evaluated as N/L short IFFTs
-  int32_t pad0;
+  int32_t n_long_sb;         // RX: subbands whose short IFFT needs the whole workgroup (L > 1024)
 };
 
 // One FC block of a group.

@@ -257,6 +257,8 @@ void build_op(fc_plan* P, int kind) {
     // RX: spread the one-wave short IFFTs (L <= 1024) over the four waves,
     // largest first onto the least loaded wave
     if (kind != 0) {
+      for (int i = 0; i < gd.n_sb; ++i)
+        if (op.sb[gd.sb_first + i].L > 1024) op.grp.back().n_long_sb++;
       std::vector<int> idx;
       for (int i = 0; i < gd.n_sb; ++i)
         if (op.sb[gd.sb_first + i].L <= 1024) idx.push_back(gd.sb_first + i);
@@ -385,12 +387,18 @@ void build_op(fc_plan* P, int kind) {
         }
       }
     } else {
-      // --- RX tasks: one block each ---
+      // --- RX tasks: runs of consecutive blocks (the next block's input is
+      // prefetched while the current one is analysed); in accumulate mode
+      // single blocks, split into even and odd launches so no two tasks of a
+      // launch add into the same low-rate samples ---
       const bool acc = !G.sync && ((kind == 1 && G.ola) || (kind == 2 && !G.ola));
       any_ola_rx |= acc;
-      for (int b = 0; b < nblk; ++b) {
+      int64_t total_blocks = 0;
+      for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
+      const int K = acc ? 1 : (int)std::max<int64_t>(2, std::min<int64_t>(8, total_blocks / 4096));
+      for (int b = 0; b < nblk; b += K) {
         TaskDesc t{};
-        t.group = (int)g; t.blk_first = first_blk + b; t.blk_count = 1;
+        t.group = (int)g; t.blk_first = first_blk + b; t.blk_count = std::min(K, nblk - b);
         t.accumulate = acc ? 1 : 0;
         PhaseTasks& ph = acc ? ((b & 1) ? rx_odd : rx_even) : rx_all;
         ClassTasks& ct = ph.cls[std::make_tuple(2, N, 0)];

@@ -462,11 +462,24 @@ struct TxEpi : NoPrefetch {
   }
 };
 
-// RX: long-FFT result into the LDS spectrum (natural order).
-struct StoreLds : NoPrefetch {
-  float2* s;
-  __device__ __forceinline__ void operator()(int, int t, float2 v) const { s[t] = v; }
+// RX, last pass of the long FFT: each bin q goes straight to every subband
+// region that gathers it (up to four LDS destinations per bin, 16 bits each,
+// 0xffff = none; built by the planner). The regions overlay the spectrum: all
+// reads of the last pass finished at its barrier. The destinations are read
+// (from cache) only when the bins are stored: holding them through the
+// transform would cost 32 registers per thread and one wave per SIMD.
+struct StoreScatter : NoPrefetch {
+  float2* S; const uint64_t* map;
+  __device__ __forceinline__ void operator()(int, int t, float2 v) const {
+    const uint64_t e = map[t];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t d = (uint32_t)(e >> (16 * k)) & 0xffffu;
+      if (d != 0xffffu) S[d] = v;
+    }
+  }
 };
+
 
 // High-rate segment with an input window [lo, hi).
 template <int IO> struct LoadHigh : NoPrefetch {
@@ -476,10 +489,12 @@ template <int IO> struct LoadHigh : NoPrefetch {
   }
 };
 
-// RX short IFFT first pass: bin u of the subband (inverse shift) gathers long
-// bin q = (q0 + p) mod N, p = (u + L/2) mod L, weighted by D[p] and conj phase.
-template <int NT, int L, int N> struct LoadGather {
-  const float2* S; const float* D; float2 ph; int q0;
+
+// RX short IFFT first pass from the subband's compacted region (bin u of the
+// subband at region[pad(u)], already in inverse-shift order), weighted by
+// D[p] and the conj phase; the transform then runs in place in the region.
+template <int NT, int L> struct LoadCompact {
+  const float2* R; const float* D; float2 ph;
   float d[16];
   __device__ __forceinline__ void prefetch(int tid) {
 #pragma unroll
@@ -489,8 +504,7 @@ template <int NT, int L, int N> struct LoadGather {
     }
   }
   __device__ __forceinline__ float2 operator()(int slot, int u, int) const {
-    const int p = (u + (L >> 1)) & (L - 1);
-    return cscale(cmul(S[(q0 + p) & (N - 1)], ph), d[slot]);
+    return cscale(cmul(R[pad(u)], ph), d[slot]);
   }
 };
 
@@ -674,12 +688,13 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
 
 // ------------------------------------------------------------- RX tasks ---
 // A run of consecutive blocks per task. Per block: the long FFT on the whole
-// workgroup, then every subband's gather + short IFFT. Subbands with
-// L <= 1024 run as one-wave transforms on the wave the planner chose
-// (balanced over the four waves); longer ones use the whole workgroup. The
-// next block's input is loaded into registers while the subbands run.
+// workgroup, whose last pass scatters every bin into the LDS region of each
+// subband that gathers it (inverse-shift order; the regions overlay the
+// spectrum); then each subband's short IFFT runs in place in its region: subbands with L <= 1024 as one-wave transforms on the wave the
+// planner chose, longer ones on the whole workgroup. The next block's input
+// is loaded into registers while the subbands run.
 template <int IO, int NL>
-__global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax) {
+__global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int) {
   extern __shared__ float2 smem[];
   // consecutive tasks (runs sharing input at their boundary) go to the same
   // XCD: the dispatcher places workgroup i on XCD i mod 8
@@ -689,11 +704,10 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax)
   if (task >= a.n_task) return;
   const TaskDesc T = a.task[task];
   const GroupDesc G = a.grp[T.group];
-  float2* S = smem;                                        // long spectrum (N)
+  float2* S = smem;                                        // long spectrum, then subband regions
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  float2* ws = smem + lds_elems(NL) + wave * lds_elems(wmax);   // this wave's scratch
-  float2* bs = smem + lds_elems(NL);                       // workgroup scratch (long subbands)
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
+  const uint64_t* map = a.rxmap + G.map_off;
   LoadAhead<IO, kThreads, NL> lh;
   {
     const BlockDesc B0 = a.blk[T.blk_first];
@@ -701,10 +715,10 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax)
   }
   for (int bi = 0; bi < T.blk_count; ++bi) {
     const BlockDesc B = a.blk[T.blk_first + bi];
-    StoreLds sl;
-    sl.s = S;
+    StoreScatter sc;
+    sc.S = S; sc.map = map;
     __syncthreads();
-    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sl, tw);
+    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sc, tw);
     if (bi + 1 < T.blk_count) {
       const BlockDesc Bn = a.blk[T.blk_first + bi + 1];
       lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
@@ -719,10 +733,9 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax)
           const BlockSb Z = a.bsb[B.bs + m];
           StoreLow<IO> so;
           so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
-          LoadGather<64, LL, NL> lg;
-          lg.S = S; lg.D = a.weights + Sb.w_off; lg.ph = make_float2(Z.ph.x, Z.ph.y); lg.q0 = Sb.q0;
-          wave_sync();
-          fft_run<64, LL, 0, +1>(ws, lane, lg, so, tw);
+          LoadCompact<64, LL> lc2;
+          lc2.R = S + Sb.cofs; lc2.D = a.weights + Sb.w_off; lc2.ph = make_float2(Z.ph.x, Z.ph.y);
+          fft_run<64, LL, 0, +1>(S + Sb.cofs, lane, lc2, so, tw);
         }
       }
     };
@@ -737,10 +750,10 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int wmax)
           const BlockSb Z = a.bsb[B.bs + m];
           StoreLow<IO> so;
           so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
-          LoadGather<kThreads, LL, NL> lg;
-          lg.S = S; lg.D = a.weights + Sb.w_off; lg.ph = make_float2(Z.ph.x, Z.ph.y); lg.q0 = Sb.q0;
+          LoadCompact<kThreads, LL> lc2;
+          lc2.R = S + Sb.cofs; lc2.D = a.weights + Sb.w_off; lc2.ph = make_float2(Z.ph.x, Z.ph.y);
           __syncthreads();
-          fft_run<kThreads, LL, 0, +1>(bs, tid, lg, so, tw);
+          fft_run<kThreads, LL, 0, +1>(S + Sb.cofs, tid, lc2, so, tw);
         }
       }
     };

@@ -9,6 +9,8 @@ namespace fcx {
 constexpr int kThreads = 256;
 constexpr int kMaxPoints = 4096;
 constexpr int kTwiddleN = 4096;      // global twiddle table: exp(-j 2 pi k / 4096)
+constexpr int kRxMaxDest = 4;        // RX: LDS destinations per long-FFT bin
+constexpr int kRxMaxLds = 8192;      // RX: LDS entries available to one group's subband regions
 
 enum IoType : int32_t { IO_C64 = 0, IO_F16 = 1, IO_BF16 = 2 };
 
@@ -59,6 +61,8 @@ struct SbDesc {
   int32_t q0;             // (c_m - L_m/2) mod N: long bin of shifted index p = 0
   int32_t w_off;          // offset of this subband's weights in the weight table
   int32_t wave;           // RX: wave (0..3) running this subband's short IFFT, -1: whole workgroup
+  int32_t cofs;           // RX: LDS offset of this subband's region after compaction
+  int32_t pad1;
   int64_t lo_off;         // element offset of the subband's low-rate data for this op
   int64_t lo_len;         // number of low-rate samples for this op
 };
@@ -69,6 +73,8 @@ struct GroupDesc {
   int32_t n_sb, sb_first;    // subbands [sb_first, sb_first + n_sb) of the op's table
   int32_t prune;             // TX: 1 when the long IFFT is evaluated as N/L short IFFTs
   int32_t n_long_sb;         // RX: subbands whose short IFFT needs the whole workgroup (L > 1024)
+  int32_t map_off;           // RX: offset of the group's scatter map (N entries) in LaunchArgs::rxmap
+  int32_t pad1;
 };
 
 // One FC block of a group.
@@ -110,6 +116,7 @@ struct LaunchArgs {
   const float* weights;
   const Cf* twiddle;         // exp(-j 2 pi k / kTwiddleN), k < kTwiddleN
   const Cf* twpass;          // per-pass twiddle bases (device code's twb_off layout)
+  const uint64_t* rxmap;     // RX scatter maps: per long bin up to four 16-bit LDS destinations
   unsigned int* counter;     // work counter (reset by the preceding reset kernel)
   const void* in;
   void* out;

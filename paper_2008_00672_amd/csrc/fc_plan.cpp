@@ -82,6 +82,7 @@ struct Op {
   std::vector<BlockDesc> blk;
   std::vector<BlockSb> bsb;
   std::vector<TaskDesc> task;
+  std::vector<uint64_t> rxmap;            // RX scatter maps
   // One kernel launch. kind: 0 = FC kernel of class cls (0 TX pruned, 1 TX
   // full, 2 RX) and transform size `size`; 2 = zero the output buffer.
   struct Phase { int kind; int first, count; size_t lds; int aux; int64_t zero_n; int cls, size; };
@@ -89,6 +90,7 @@ struct Op {
   // device copies
   SbDesc* d_sb = nullptr; GroupDesc* d_grp = nullptr; BlockDesc* d_blk = nullptr;
   BlockSb* d_bsb = nullptr; TaskDesc* d_task = nullptr;
+  uint64_t* d_rxmap = nullptr;
 };
 
 }  // namespace
@@ -233,35 +235,84 @@ void build_op(fc_plan* P, int kind) {
     const int64_t len = (kind == 1 && s.sync) ? (int64_t)s.d.n_symbols * s.L : s.n_in;
     op.lo_off[m + 1] = op.lo_off[m] + len;
   }
-  // subband table in group order
-  std::vector<int> sb_index(nsb, -1);
+  // processing groups of this operation: the plan's groups, except that an RX
+  // group whose subbands exceed what one workgroup holds in LDS is split
+  // (each part repeats the long FFT)
+  struct OpGroup { int pg; std::vector<int> subs; };
+  std::vector<OpGroup> ogroups;
   for (size_t g = 0; g < P->groups.size(); ++g) {
     const Group& G = P->groups[g];
+    if (kind == 0) { ogroups.push_back(OpGroup{(int)g, G.subs}); continue; }
+    // RX: split so that each part's subband regions fit kRxMaxLds LDS entries
+    // and no long bin feeds more than kRxMaxDest of its subbands
+    OpGroup cur{(int)g, {}};
+    int acc = 0;
+    std::vector<int> mult(G.N, 0);
+    for (int m : G.subs) {
+      const Sub& s = P->subs[m];
+      const int q0 = (int)imod((int64_t)s.d.center_bin - s.L / 2, s.N);
+      bool over = acc + lds_elems(s.L) > kRxMaxLds;
+      for (int p = 0; p < s.L && !over; ++p) over = mult[(q0 + p) & (G.N - 1)] >= kRxMaxDest;
+      if (!cur.subs.empty() && over) {
+        ogroups.push_back(cur);
+        cur.subs.clear();
+        acc = 0;
+        std::fill(mult.begin(), mult.end(), 0);
+      }
+      cur.subs.push_back(m);
+      acc += lds_elems(s.L);
+      for (int p = 0; p < s.L; ++p) mult[(q0 + p) & (G.N - 1)]++;
+    }
+    ogroups.push_back(cur);
+  }
+  // subband table in group order
+  for (size_t g = 0; g < ogroups.size(); ++g) {
+    const OpGroup& OG = ogroups[g];
+    const Group& G = P->groups[OG.pg];
     GroupDesc gd{};
     gd.N = G.N; gd.logN = ilog2(G.N);
-    gd.n_sb = (int)G.subs.size(); gd.sb_first = (int)op.sb.size();
-    const Sub& s0 = P->subs[G.subs[0]];
-    gd.prune = (kind == 0 && G.subs.size() == 1 && s0.I >= 2 && s0.L >= 16) ? 1 : 0;
+    gd.n_sb = (int)OG.subs.size(); gd.sb_first = (int)op.sb.size();
+    const Sub& s0 = P->subs[OG.subs[0]];
+    gd.prune = (kind == 0 && OG.subs.size() == 1 && s0.I >= 2 && s0.L >= 16) ? 1 : 0;
     op.grp.push_back(gd);
-    for (int m : G.subs) {
+    int cofs = 0;
+    for (int m : OG.subs) {
       const Sub& s = P->subs[m];
       SbDesc d{};
       d.L = s.L; d.logL = s.logL; d.c = s.d.center_bin;
       d.q0 = (int)imod((int64_t)s.d.center_bin - s.L / 2, s.N);
       d.w_off = P->w_off[m];
       d.wave = -1;
+      d.cofs = cofs;
+      cofs += lds_elems(s.L);
       d.lo_off = op.lo_off[m]; d.lo_len = op.lo_off[m + 1] - op.lo_off[m];
-      sb_index[m] = (int)op.sb.size();
       op.sb.push_back(d);
     }
-    // RX: spread the one-wave short IFFTs (L <= 1024) over the four waves,
-    // largest first onto the least loaded wave
     if (kind != 0) {
-      for (int i = 0; i < gd.n_sb; ++i)
-        if (op.sb[gd.sb_first + i].L > 1024) op.grp.back().n_long_sb++;
+      GroupDesc& gr = op.grp.back();
+      // scatter map: long bin q feeds IFFT input u = (p + L/2) mod L of every
+      // subband with p = (q - q0) mod N < L, at LDS cofs + pad(u)
+      gr.map_off = (int)op.rxmap.size();
+      op.rxmap.resize(op.rxmap.size() + gr.N, ~0ull);
+      std::vector<int> cnt(gr.N, 0);
+      for (int i = 0; i < gr.n_sb; ++i) {
+        const SbDesc& d = op.sb[gr.sb_first + i];
+        for (int pidx = 0; pidx < d.L; ++pidx) {
+          const int q = (d.q0 + pidx) & (gr.N - 1);
+          const int u = (pidx + d.L / 2) & (d.L - 1);
+          const uint64_t dst = (uint64_t)(d.cofs + u + (u >> 5));
+          uint64_t& e = op.rxmap[gr.map_off + q];
+          e &= ~(0xffffull << (16 * cnt[q]));
+          e |= dst << (16 * cnt[q]);
+          cnt[q]++;
+        }
+        if (d.L > 1024) gr.n_long_sb++;
+      }
+      // spread the one-wave short IFFTs (L <= 1024) over the four waves,
+      // largest first onto the least loaded wave
       std::vector<int> idx;
-      for (int i = 0; i < gd.n_sb; ++i)
-        if (op.sb[gd.sb_first + i].L <= 1024) idx.push_back(gd.sb_first + i);
+      for (int i = 0; i < gr.n_sb; ++i)
+        if (op.sb[gr.sb_first + i].L <= 1024) idx.push_back(gr.sb_first + i);
       std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return op.sb[x].L > op.sb[y].L; });
       double load[4] = {0, 0, 0, 0};
       for (int i : idx) {
@@ -277,14 +328,18 @@ void build_op(fc_plan* P, int kind) {
   std::map<int, PhaseTasks> tx_phase;        // TX: by group rank within the stream
   PhaseTasks rx_all, rx_even, rx_odd;
   bool any_acc_tx = false, any_ola_rx = false;
-  for (size_t g = 0; g < P->groups.size(); ++g) {
-    const Group& G = P->groups[g];
-    const Sub& s0 = P->subs[G.subs[0]];
+  for (size_t g = 0; g < ogroups.size(); ++g) {
+    const OpGroup& OG = ogroups[g];
+    const Group& G = P->groups[OG.pg];
+    const Sub& s0 = P->subs[OG.subs[0]];
     const int N = G.N;
     const int64_t base = P->hi_off[G.stream] + G.offset;
     const int first_blk = (int)op.blk.size();
-    int lmax = 0;
-    for (int m : G.subs) lmax = std::max(lmax, P->subs[m].L);
+    int lmax = 0, lsum = 0;
+    for (int m : OG.subs) {
+      lmax = std::max(lmax, P->subs[m].L);
+      lsum += lds_elems(P->subs[m].L);
+    }
     // --- blocks ---
     const int nblk = G.sync ? 2 * s0.d.n_symbols : G.R;
     for (int b = 0; b < nblk; ++b) {
@@ -306,7 +361,7 @@ void build_op(fc_plan* P, int kind) {
       }
       bd.bs = (int)op.bsb.size();
       op.blk.push_back(bd);
-      for (int m : G.subs) {
+      for (int m : OG.subs) {
         const Sub& s = P->subs[m];
         const int L = s.L;
         BlockSb z{};
@@ -403,13 +458,7 @@ void build_op(fc_plan* P, int kind) {
         PhaseTasks& ph = acc ? ((b & 1) ? rx_odd : rx_even) : rx_all;
         ClassTasks& ct = ph.cls[std::make_tuple(2, N, 0)];
         ct.t.push_back(t);
-        int wmax = 0, lbig = 0;
-        for (int m : G.subs) {
-          const int L = P->subs[m].L;
-          if (L <= 1024) wmax = std::max(wmax, L); else lbig = std::max(lbig, L);
-        }
-        ct.aux = std::max(ct.aux, wmax);
-        ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + std::max(4 * lds_elems(ct.aux), lds_elems(lbig))) * 8);
+        ct.lds = std::max(ct.lds, (size_t)std::max(lds_elems(N), lsum) * 8);
       }
     }
   }
@@ -460,11 +509,14 @@ fc_status upload_op(Op& op) {
   if ((s = upload(op.blk, &op.d_blk))) return s;
   if ((s = upload(op.bsb, &op.d_bsb))) return s;
   if ((s = upload(op.task, &op.d_task))) return s;
+  if ((s = upload(op.rxmap, &op.d_rxmap))) return s;
   return FC_OK;
 }
 
 void free_op(Op& op) {
   hipFree(op.d_sb); hipFree(op.d_grp); hipFree(op.d_blk); hipFree(op.d_bsb); hipFree(op.d_task);
+  hipFree(op.d_rxmap);
+  op.d_rxmap = nullptr;
   op.d_sb = nullptr; op.d_grp = nullptr; op.d_blk = nullptr; op.d_bsb = nullptr; op.d_task = nullptr;
 }
 
@@ -484,7 +536,8 @@ fc_status run_op(fc_plan* P, int kind, const void* in, void* out, hipStream_t st
       LaunchArgs a{};
       a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
       a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
-      a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.counter = nullptr;
+      a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
+      a.counter = nullptr;
       a.in = in; a.out = out;
       e = launch_kernel(ph.cls, ph.size, a, ph.aux, ph.lds, st);
     }

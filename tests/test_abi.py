@@ -88,6 +88,26 @@ def test_block_counts():
     assert _plan([s]).stats(fc.OP_TX)["blocks"] == 4
 
 
+# Subbands of one group whose RX work cannot share one workgroup: six windows
+# over the same long bins (each bin feeds at most four subbands in one pass),
+# and four L = 2048 subbands (their LDS regions exceed 8192 entries).
+RX_SPLIT = {
+    "six_overlapping": [W.subband(15, 2, 24, 4, 64, 256, c, "sync_ola") for c in (-12, -6, 0, 6, 12, 18)],
+    "four_long": [W.subband(15, 2, 1000, 16, 2048, 4096, c, "sync_ola") for c in (-1000, -300, 300, 1000)],
+}
+
+
+@pytest.mark.parametrize("name", sorted(RX_SPLIT))
+def test_rx_group_split(name):
+    """TX keeps one group (one long transform per block); RX and the adjoint
+    repeat the long transform in a second part."""
+    fc = _lib()
+    p = _plan(RX_SPLIT[name])
+    assert p.stats(fc.OP_TX)["blocks"] == 4
+    assert p.stats(fc.OP_RX)["blocks"] == 8
+    assert p.stats(fc.OP_ADJ)["blocks"] == 8
+
+
 BAD = {
     "short_not_pow2": (dict(n_short=96), "FC_E_UNSUPPORTED"),
     "long_too_big": (dict(n_long=8192), "FC_E_UNSUPPORTED"),

@@ -111,6 +111,21 @@ TINY_RX = {
 }
 
 
+# groups that RX splits into parts (bins feeding more than four subbands;
+# subband regions beyond one workgroup's LDS)
+RX_SPLIT = {
+    "six_overlapping": [W.subband(15, 2, 24, 4, 64, 256, c, "sync_ola") for c in (-12, -6, 0, 6, 12, 18)],
+    "four_long": [W.subband(15, 2, 1000, 16, 2048, 4096, c, "sync_ola") for c in (-1000, -300, 300, 1000)],
+}
+
+
+@pytest.mark.parametrize("name", sorted(RX_SPLIT))
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_rx_split_groups(name, adjoint):
+    got, ref = run_rx(RX_SPLIT[name], "c64", seed=9, weights="random", adjoint=adjoint)
+    assert_gate(got, ref, "c64", name)
+
+
 @pytest.mark.parametrize("name", sorted(TINY_RX))
 def test_rx_tiny(name):
     got, ref = run_rx(TINY_RX[name], "c64", seed=3, weights="random")

@@ -7,3 +7,9 @@ the library has not been built.
 """
 from .fc import (Plan, FcError, lib, CONT_OLA, CONT_OLS, SYNC_OLA, SYNC_OLS,  # noqa: F401
                  OP_TX, OP_RX, OP_ADJ)
+
+
+def fc_tx(plan, x, w):
+    """Differentiable FC synthesis (see ``autograd``)."""
+    from .autograd import fc_tx as _f
+    return _f(plan, x, w)

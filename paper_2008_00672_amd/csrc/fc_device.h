@@ -764,6 +764,106 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int) {
   }
 }
 
+// ---------------------------------------------------- weight gradient ---
+// Last pass of the short FFT of the forward input block: bin u (natural
+// order, weight index p = (u + L/2) mod L) adds Re(conj(A) X) to its LDS
+// accumulator, where A = G(Xi(p)) * phase is the adjoint's value for that bin
+// before the weight (G the long FFT of the gradient block, held in the
+// subband's region) and X the forward short-FFT bin.
+struct StoreGrad : NoPrefetch {
+  const float2* R; float2 ph; float* acc;
+  __device__ __forceinline__ void operator()(int, int u, float2 x) const {
+    const float2 a = cmul(R[pad(u)], ph);
+    acc[u] += a.x * x.x + a.y * x.y;
+  }
+};
+
+// Per block, as the adjoint: long FFT of the gradient block scattered into
+// the subband regions; then per subband the short FFT of the forward input
+// block (window and phase of the forward transform) in a scratch buffer,
+// whose last pass accumulates the products. Each accumulator belongs to one
+// thread for the whole task; at the end the task adds its sums into grad_w
+// (float atomics: tasks of one subband run concurrently).
+template <int IO, int NL>
+__global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
+  extern __shared__ float2 smem[];
+  const int n = gridDim.x;
+  int task = blockIdx.x;
+  if ((n & 7) == 0) task = (blockIdx.x & 7) * (n >> 3) + (blockIdx.x >> 3);
+  if (task >= a.n_task) return;
+  const TaskDesc T = a.task[task];
+  const GroupDesc G = a.grp[T.group];
+  float2* S = smem;
+  float2* scr = smem + G.scr_off;
+  float* acc = reinterpret_cast<float*>(smem + G.acc_off);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const float2* tw = reinterpret_cast<const float2*>(a.twpass);
+  const uint64_t* map = a.rxmap + G.map_off;
+  for (int i = tid; i < G.acc_len; i += kThreads) acc[i] = 0.f;
+  LoadAhead<IO, kThreads, NL> lh;
+  {
+    const BlockDesc B0 = a.blk[T.blk_first];
+    lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
+  }
+  for (int bi = 0; bi < T.blk_count; ++bi) {
+    const BlockDesc B = a.blk[T.blk_first + bi];
+    StoreScatter sc;
+    sc.S = S; sc.map = map;
+    __syncthreads();
+    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sc, tw);
+    if (bi + 1 < T.blk_count) {
+      const BlockDesc Bn = a.blk[T.blk_first + bi + 1];
+      lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
+    }
+    __syncthreads();
+    auto run_wave = [&](auto lc) {
+      constexpr int LL = decltype(lc)::value;
+      if constexpr (LL <= NL) {
+        for (int m = 0; m < G.n_sb; ++m) {
+          const SbDesc Sb = a.sb[G.sb_first + m];
+          if (Sb.L != LL || Sb.wave != wave) continue;
+          const BlockSb Z = a.bsb[B.bs + m];
+          LoadSeg<IO> ls;
+          ls.x = at<IO>(a.in2, Z.x0); ls.lo = Z.lo; ls.hi = Z.hi;
+          StoreGrad sg;
+          sg.R = S + Sb.cofs; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = acc + Sb.aofs;
+          wave_sync();
+          fft_run<64, LL, 0, -1>(scr + wave * G.wstride, lane, ls, sg, tw);
+        }
+      }
+    };
+    run_wave(SizeC<1024>()); run_wave(SizeC<512>()); run_wave(SizeC<256>()); run_wave(SizeC<128>());
+    run_wave(SizeC<64>()); run_wave(SizeC<32>()); run_wave(SizeC<16>());
+    auto run_group = [&](auto lc) {
+      constexpr int LL = decltype(lc)::value;
+      if constexpr (LL <= NL) {
+        for (int m = 0; m < G.n_sb; ++m) {
+          const SbDesc Sb = a.sb[G.sb_first + m];
+          if (Sb.L != LL || Sb.wave >= 0) continue;
+          const BlockSb Z = a.bsb[B.bs + m];
+          LoadSeg<IO> ls;
+          ls.x = at<IO>(a.in2, Z.x0); ls.lo = Z.lo; ls.hi = Z.hi;
+          StoreGrad sg;
+          sg.R = S + Sb.cofs; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = acc + Sb.aofs;
+          __syncthreads();
+          fft_run<kThreads, LL, 0, -1>(scr, tid, ls, sg, tw);
+        }
+      }
+    };
+    if (G.n_long_sb > 0) {
+      run_group(SizeC<2048>());
+      run_group(SizeC<4096>());
+    }
+  }
+  __syncthreads();
+  float* gw = reinterpret_cast<float*>(a.out);
+  for (int m = 0; m < G.n_sb; ++m) {
+    const SbDesc Sb = a.sb[G.sb_first + m];
+    for (int u = tid; u < Sb.L; u += kThreads)
+      atomicAdd(gw + Sb.w_off + ((u + (Sb.L >> 1)) & (Sb.L - 1)), acc[Sb.aofs + u]);
+  }
+}
+
 template <int IO>
 __global__ __launch_bounds__(kThreads) void fc_zero_kernel(void* out, int64_t n) {
   typename Io<IO>::T* p = at<IO>(out, 0);
@@ -774,7 +874,8 @@ __global__ __launch_bounds__(kThreads) void fc_zero_kernel(void* out, int64_t n)
 
 // ------------------------------------------------------ per-I/O dispatch ---
 // Kernel classes: 0 = TX pruned (size = L, aux = log2 I), 1 = TX full
-// (size = N, aux = largest L), 2 = RX (size = N, aux = largest one-wave L).
+// (size = N, aux = largest L), 2 = RX and adjoint (size = N), 3 = weight
+// gradient (size = N).
 template <int IO, int L>
 hipError_t launch_pruned(const LaunchArgs& a, int logi, size_t lds, hipStream_t s, dim3 grid) {
   dim3 block(kThreads);
@@ -794,6 +895,8 @@ hipError_t launch_size(int cls, const LaunchArgs& a, int aux, size_t lds, hipStr
   if (cls == 0) return launch_pruned<IO, SZ>(a, aux, lds, s, grid);
   if (cls == 1) {
     hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ>), grid, block, lds, s, a, aux);
+  } else if (cls == 3) {
+    hipLaunchKernelGGL((fc_wgrad_kernel<IO, SZ>), grid, block, lds, s, a, aux);
   } else {
     hipLaunchKernelGGL((fc_rx_kernel<IO, SZ>), grid, block, lds, s, a, aux);
   }
@@ -803,7 +906,7 @@ hipError_t launch_size(int cls, const LaunchArgs& a, int aux, size_t lds, hipStr
 template <int IO>
 hipError_t launch_io(int cls, int size, const LaunchArgs& a, int aux, size_t lds, hipStream_t s) {
   if (a.n_task <= 0) return hipSuccess;
-  dim3 grid(cls == 2 ? ((a.n_task + 7) & ~7) : a.n_task);
+  dim3 grid(cls >= 2 ? ((a.n_task + 7) & ~7) : a.n_task);
   switch (size) {
 #define FC_SZ(SZ) case SZ: return launch_size<IO, SZ>(cls, a, aux, lds, s, grid);
     FC_SZ(16) FC_SZ(32) FC_SZ(64) FC_SZ(128) FC_SZ(256) FC_SZ(512) FC_SZ(1024) FC_SZ(2048) FC_SZ(4096)
@@ -844,9 +947,12 @@ hipError_t lds_limits_io(size_t bytes) {
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
     hipError_t r3 = hipFuncSetAttribute((const void*)fc_rx_kernel<IO, SZ>,                          \
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
+    hipError_t r4 = hipFuncSetAttribute((const void*)fc_wgrad_kernel<IO, SZ>,                       \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
     if (r1 != hipSuccess) e = r1;                                                                   \
     if (r2 != hipSuccess) e = r2;                                                                   \
     if (r3 != hipSuccess) e = r3;                                                                   \
+    if (r4 != hipSuccess) e = r4;                                                                   \
   }
   FC_SZ(16) FC_SZ(32) FC_SZ(64) FC_SZ(128) FC_SZ(256) FC_SZ(512) FC_SZ(1024) FC_SZ(2048) FC_SZ(4096)
 #undef FC_SZ

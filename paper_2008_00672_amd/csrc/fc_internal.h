@@ -61,8 +61,8 @@ struct SbDesc {
   int32_t q0;             // (c_m - L_m/2) mod N: long bin of shifted index p = 0
   int32_t w_off;          // offset of this subband's weights in the weight table
   int32_t wave;           // RX: wave (0..3) running this subband's short IFFT, -1: whole workgroup
-  int32_t cofs;           // RX: LDS offset of this subband's region after compaction
-  int32_t pad1;
+  int32_t cofs;           // RX: LDS offset (complex entries) of this subband's region
+  int32_t aofs;           // weight gradient: offset (floats) of the subband's LDS accumulators
   int64_t lo_off;         // element offset of the subband's low-rate data for this op
   int64_t lo_len;         // number of low-rate samples for this op
 };
@@ -74,6 +74,10 @@ struct GroupDesc {
   int32_t prune;             // TX: 1 when the long IFFT is evaluated as N/L short IFFTs
   int32_t n_long_sb;         // RX: subbands whose short IFFT needs the whole workgroup (L > 1024)
   int32_t map_off;           // RX: offset of the group's scatter map (N entries) in LaunchArgs::rxmap
+  int32_t scr_off;           // weight gradient: LDS offset (complex entries) of the short-FFT scratch
+  int32_t wstride;           // weight gradient: scratch entries per wave (one-wave transforms)
+  int32_t acc_off;           // weight gradient: LDS offset (complex entries) of the accumulators
+  int32_t acc_len;           // weight gradient: accumulator floats (sum of the subbands' L)
   int32_t pad1;
 };
 
@@ -117,9 +121,9 @@ struct LaunchArgs {
   const Cf* twiddle;         // exp(-j 2 pi k / kTwiddleN), k < kTwiddleN
   const Cf* twpass;          // per-pass twiddle bases (device code's twb_off layout)
   const uint64_t* rxmap;     // RX scatter maps: per long bin up to four 16-bit LDS destinations
-  unsigned int* counter;     // work counter (reset by the preceding reset kernel)
   const void* in;
   void* out;
+  const void* in2;           // weight gradient: the forward low-rate input
 };
 
 }  // namespace fcx

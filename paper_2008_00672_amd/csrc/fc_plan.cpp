@@ -84,8 +84,10 @@ struct Op {
   std::vector<TaskDesc> task;
   std::vector<uint64_t> rxmap;            // RX scatter maps
   // One kernel launch. kind: 0 = FC kernel of class cls (0 TX pruned, 1 TX
-  // full, 2 RX) and transform size `size`; 2 = zero the output buffer.
-  struct Phase { int kind; int first, count; size_t lds; int aux; int64_t zero_n; int cls, size; };
+  // full, 2 RX / adjoint) and transform size `size`; 2 = zero the output
+  // buffer. glds: LDS bytes of the weight-gradient kernel over the same tasks
+  // (adjoint op only).
+  struct Phase { int kind; int first, count; size_t lds; int aux; int64_t zero_n; int cls, size; size_t glds; };
   std::vector<Phase> phases;
   // device copies
   SbDesc* d_sb = nullptr; GroupDesc* d_grp = nullptr; BlockDesc* d_blk = nullptr;
@@ -320,10 +322,25 @@ void build_op(fc_plan* P, int kind) {
         op.sb[i].wave = w;
         load[w] += (double)op.sb[i].L * (op.sb[i].logL + 1);
       }
+      // weight-gradient LDS: spectrum / regions, short-FFT scratch (one per
+      // wave, or one workgroup buffer for L > 1024), float accumulators
+      int rsum = 0, wmax = 0, lmax_long = 0;
+      gr.acc_len = 0;
+      for (int i = 0; i < gr.n_sb; ++i) {
+        SbDesc& d = op.sb[gr.sb_first + i];
+        rsum += lds_elems(d.L);
+        if (d.L <= 1024) wmax = std::max(wmax, d.L);
+        else lmax_long = std::max(lmax_long, d.L);
+        d.aofs = gr.acc_len;
+        gr.acc_len += d.L;
+      }
+      gr.wstride = wmax ? lds_elems(wmax) : 0;
+      gr.scr_off = std::max(lds_elems(gr.N), rsum);
+      gr.acc_off = gr.scr_off + std::max(4 * gr.wstride, lmax_long ? lds_elems(lmax_long) : 0);
     }
   }
   // blocks and tasks; tasks are collected per launch phase and kernel class
-  struct ClassTasks { std::vector<TaskDesc> t; size_t lds = 0; int aux = 0; };
+  struct ClassTasks { std::vector<TaskDesc> t; size_t lds = 0; int aux = 0; size_t glds = 0; };
   struct PhaseTasks { std::map<std::tuple<int, int, int>, ClassTasks> cls; };
   std::map<int, PhaseTasks> tx_phase;        // TX: by group rank within the stream
   PhaseTasks rx_all, rx_even, rx_odd;
@@ -459,6 +476,8 @@ void build_op(fc_plan* P, int kind) {
         ClassTasks& ct = ph.cls[std::make_tuple(2, N, 0)];
         ct.t.push_back(t);
         ct.lds = std::max(ct.lds, (size_t)std::max(lds_elems(N), lsum) * 8);
+        const GroupDesc& gd = op.grp[g];
+        ct.glds = std::max(ct.glds, (size_t)(gd.acc_off + (gd.acc_len + 1) / 2) * 8);
       }
     }
   }
@@ -484,16 +503,16 @@ void build_op(fc_plan* P, int kind) {
         });
       }
       Op::Phase p{0, (int)op.task.size(), (int)ct.t.size(), ct.lds, ct.aux, 0, std::get<0>(kv.first),
-                  std::get<1>(kv.first)};
+                  std::get<1>(kv.first), ct.glds};
       op.task.insert(op.task.end(), ct.t.begin(), ct.t.end());
       op.phases.push_back(p);
     }
   };
   if (kind == 0) {
-    if (any_acc_tx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, P->hi_off.back(), 0, 0});
+    if (any_acc_tx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, P->hi_off.back(), 0, 0, 0});
     for (auto& kv : tx_phase) emit(kv.second, true);
   } else {
-    if (any_ola_rx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, op.lo_off.back(), 0, 0});
+    if (any_ola_rx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, op.lo_off.back(), 0, 0, 0});
     // RX tasks keep block order (neighbouring blocks share input in L2)
     emit(rx_all, false);
     emit(rx_even, false);
@@ -537,11 +556,36 @@ fc_status run_op(fc_plan* P, int kind, const void* in, void* out, hipStream_t st
       a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
       a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
       a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
-      a.counter = nullptr;
       a.in = in; a.out = out;
       e = launch_kernel(ph.cls, ph.size, a, ph.aux, ph.lds, st);
     }
     if (e != hipSuccess) { result = FC_E_DEVICE; break; }
+  }
+  if (cur != P->device) hipSetDevice(cur);
+  return result;
+}
+
+// Weight gradient: zero grad_w, then the gradient kernel over the adjoint's
+// tasks (its blocks carry the forward windows and the adjoint phases).
+fc_status run_wgrad(fc_plan* P, const void* x, const void* g, float* grad_w, hipStream_t st) {
+  Op& op = P->op[FC_OP_ADJ];
+  if (!op.valid || P->device < 0) return FC_E_STATE;
+  if (!x || !g || !grad_w) return FC_E_ARG;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
+  if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
+  fc_status result = FC_OK;
+  // P->w_total floats (even: every L is a power of two >= 16) as complex zeros
+  if (launch_zero(grad_w, P->w_total / 2, IO_C64, st) != hipSuccess) result = FC_E_DEVICE;
+  for (const Op::Phase& ph : op.phases) {
+    if (result != FC_OK) break;
+    if (ph.kind == 2) continue;
+    LaunchArgs a{};
+    a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
+    a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
+    a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
+    a.in = g; a.out = grad_w; a.in2 = x;
+    if (launch_kernel(3, ph.size, a, ph.aux, ph.glds, st) != hipSuccess) result = FC_E_DEVICE;
   }
   if (cur != P->device) hipSetDevice(cur);
   return result;
@@ -666,7 +710,7 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   for (int k = 0; k < 3 && !st; ++k) st = upload_op(P->op[k]);
   size_t lds_max = 0;
   for (int k = 0; k < 3; ++k)
-    for (auto& ph : P->op[k].phases) lds_max = std::max(lds_max, ph.lds);
+    for (auto& ph : P->op[k].phases) lds_max = std::max(lds_max, std::max(ph.lds, ph.glds));
   if (!st && lds_max > 65536 && set_lds_limits(lds_max) != hipSuccess) st = FC_E_UNSUPPORTED;
   hipSetDevice(cur);
   if (st) { fc_plan_destroy(P); return st; }
@@ -790,9 +834,8 @@ fc_status fc_tx_adjoint(fc_plan* P, const void* in, void* out, void* stream) {
 
 fc_status fc_tx_weight_grad(fc_plan* P, const void* lowrate_in, const void* grad_out, float* grad_w,
                             void* stream) {
-  (void)lowrate_in; (void)grad_out; (void)grad_w; (void)stream;
   if (!P) return FC_E_ARG;
-  return FC_E_UNSUPPORTED;
+  return run_wgrad(P, lowrate_in, grad_out, grad_w, (hipStream_t)stream);
 }
 
 }  // extern "C"

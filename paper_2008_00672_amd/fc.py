@@ -243,8 +243,9 @@ class Plan:
         total = sum(s["n_short"] for s in self.subbands)
         if out is None:
             out = torch.empty(total, dtype=torch.float32, device=x.device)
-        if out.dtype != torch.float32 or out.numel() != total or not out.is_contiguous():
-            raise ValueError("grad_w must be a contiguous float32 tensor of sum(n_short) values")
+        if (not out.is_cuda or out.device.index != self.device or out.dtype != torch.float32
+                or out.numel() != total or not out.is_contiguous()):
+            raise ValueError("grad_w must be a contiguous float32 tensor of sum(n_short) values on the plan's device")
         _check(lib().fc_tx_weight_grad(self._h, _ptr(x), _ptr(g), _ptr(out), _stream_handle(stream)),
                "fc_tx_weight_grad")
         return out

@@ -10,6 +10,7 @@ import numpy as np
 
 import fcsynth
 from oracle import fc as ofc
+from oracle import grad as ogr
 from oracle import lin as olin
 from oracle import numerology as nu
 from oracle import weights as ow
@@ -101,6 +102,27 @@ def oracle_adj(subbands, streams, Ds):
             outs.append(ofc.rx_cont(seg, p["L"], p["N"], p["c"], Ds[i], p["n_in"], lam=p["lam"],
                                     ola=not p["ola"]))
     return outs
+
+
+def subband_forward(subband, x):
+    """D -> this subband's FC output (oracle), with its input x fixed."""
+    p = sub_params(subband)
+    if p["sync"]:
+        return lambda D: ofc.tx_sync(x, p["L"], p["N"], p["c"], D, p["ncp"])
+    return lambda D: ofc.tx_cont(x, p["L"], p["N"], p["c"], D, lam=p["lam"], ola=p["ola"])
+
+
+def oracle_wgrad(subbands, xs, g_streams, bins=None):
+    """Per subband: dJ/dD_p = Re <g, b_p> against the part of the gradient
+    stream that the subband's output occupies (``bins``: per-subband lists of
+    the bins to evaluate, default all)."""
+    off, _, P = stream_offsets(subbands)
+    out = []
+    for i, s in enumerate(subbands):
+        g = g_streams[s["stream"]][off[i]:off[i] + P[i]["Q"]]
+        out.append(ogr.weight_grad(subband_forward(s, xs[i]), g, P[i]["L"],
+                                   None if bins is None else bins[i]))
+    return out
 
 
 # -------------------------------------------------- storage conversions --

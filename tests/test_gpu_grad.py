@@ -1,0 +1,131 @@
+"""GPU weight gradient and autograd through the C ABI against the oracle.
+
+The weight gradient dJ/dD_p = Re <g, b_p> (oracle: the definition, bin by
+bin, see oracle/grad.py) is compared as a vector: 10 log10 of the squared
+error norm over the squared reference norm. Gate -90 dB: every term is a
+product of two FP32 transforms (each about -125 dB, see the parity gate)
+summed over blocks; the 35 dB margin covers cancellation in those sums.
+"""
+import numpy as np
+import pytest
+
+from fc_cases import make_inputs, oracle_adj, oracle_wgrad, stream_offsets, to_device
+from fcsynth import workloads as W
+from oracle import metrics
+from test_gpu_parity import TINY_TX, _cat, _plan, _split
+
+pytestmark = pytest.mark.gpu
+
+GRAD_GATE_DB = -90.0
+
+
+def _g_streams(subbands, seed):
+    rng = np.random.default_rng(seed)
+    _, lens, _ = stream_offsets(subbands)
+    return [rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in lens]
+
+
+def gpu_wgrad(subbands, xs, Ds, gs):
+    import torch
+    p = _plan(subbands, "c64", Ds)
+    gw = p.weight_grad(to_device(_cat(xs), "c64"), to_device(_cat(gs), "c64"))
+    torch.cuda.synchronize()
+    offs = np.cumsum([0] + [s["n_short"] for s in subbands])
+    return _split(gw.cpu().numpy().astype(np.float64), offs)
+
+
+def assert_grad(got, ref, what, bins=None):
+    for k, (g, r) in enumerate(zip(got, ref)):
+        if bins is not None:
+            g, r = g[bins[k]], r[bins[k]]
+        e = metrics.err_db(g, r)
+        print("%s subband %d: weight-gradient err %.1f dB (gate %.0f)" % (what, k, e, GRAD_GATE_DB), flush=True)
+        assert e <= GRAD_GATE_DB, "%s subband %d: %.1f dB" % (what, k, e)
+
+
+@pytest.mark.parametrize("name", sorted(TINY_TX))
+def test_weight_grad_tiny(name):
+    sbs = TINY_TX[name]
+    xs, Ds, _ = make_inputs(sbs, 16, 21, "random")
+    gs = _g_streams(sbs, 22)
+    assert_grad(gpu_wgrad(sbs, xs, Ds, gs), oracle_wgrad(sbs, xs, gs), name)
+
+
+def test_weight_grad_mixed_numerology_sampled():
+    """Both subbands of the 20 MHz mixed-numerology subframe; the oracle
+    evaluates the transition bins and a seeded sample of the others."""
+    sbs, meta = W.mixed_numerology("sync_ola")
+    xs, Ds, _ = make_inputs(sbs, meta["qam"], meta["seed"], "rc")
+    gs = _g_streams(sbs, 23)
+    rng = np.random.default_rng(24)
+    bins = []
+    for s in sbs:
+        L, K, ntb = s["n_short"], s["n_active"], s["n_tb"]
+        tb = [(K // 2 - 1 + i + L // 2) % L for i in range(1, ntb + 1)] + \
+             [(-K // 2 - i + L // 2) % L for i in range(1, ntb + 1)]
+        bins.append(sorted(set(tb) | set(rng.choice(L, 8, replace=False).tolist())))
+    ref = oracle_wgrad(sbs, xs, gs, bins)
+    assert_grad(gpu_wgrad(sbs, xs, Ds, gs), ref, "mixed numerology", bins)
+
+
+@pytest.mark.parametrize("name", ["cont_ols_16_64", "sync_ola_64_256", "two_sb_one_group"])
+def test_autograd_matches_oracle(name):
+    """J = sum |y - t|^2 through fc_tx: grad_x against the oracle adjoint of
+    g = 2 (y - t), grad_w against the oracle weight gradient of the same g."""
+    import torch
+    from paper_2008_00672_amd import Plan, fc_tx
+    sbs = TINY_TX[name]
+    xs, Ds, _ = make_inputs(sbs, 16, 31, "random")
+    plan = Plan(sbs, io="c64", device=0)
+    x = to_device(_cat(xs), "c64").requires_grad_(True)
+    w = torch.tensor(np.concatenate(Ds), dtype=torch.float32, device="cuda:0", requires_grad=True)
+    y = fc_tx(plan, x, w)
+    t = torch.randn(y.shape, dtype=torch.complex64, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(5))
+    J = (y - t).abs().pow(2).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    g = [(2.0 * (y - t)).detach().cpu().numpy().astype(np.complex128)]
+    _, lens, _ = stream_offsets(sbs)
+    g = _split(g[0], np.cumsum([0] + lens))
+    lo, _ = plan.layout(0)
+    gx_ref = oracle_adj(sbs, g, [D.astype(np.float32).astype(np.float64) for D in Ds])
+    gx = _split(x.grad.cpu().numpy().astype(np.complex128), lo)
+    for k, (a, b) in enumerate(zip(gx, gx_ref)):
+        e = metrics.err_db(a, b)
+        print("%s grad_x part %d: err %.1f dB" % (name, k, e), flush=True)
+        assert e <= -100.0
+    x64 = [xx for xx in xs]
+    gw_ref = oracle_wgrad(sbs, x64, g)
+    offs = np.cumsum([0] + [s["n_short"] for s in sbs])
+    assert_grad(_split(w.grad.cpu().numpy().astype(np.float64), offs), gw_ref, name + " autograd")
+
+
+def test_weight_grad_finite_difference_fp32():
+    """Central differences of J through the GPU forward in FP32 (h = 1e-3)
+    against the GPU weight gradient, relative error <= 1e-3 on the bins with
+    the largest gradients."""
+    import torch
+    from paper_2008_00672_amd import Plan, fc_tx
+    sbs = TINY_TX["sync_ola_64_256"]
+    xs, Ds, _ = make_inputs(sbs, 16, 41, "random")
+    plan = Plan(sbs, io="c64", device=0)
+    x = to_device(_cat(xs), "c64")
+    w0 = torch.tensor(np.concatenate(Ds), dtype=torch.float32, device="cuda:0")
+    t = torch.randn(plan.layout(0)[1][-1], dtype=torch.complex64, device="cuda:0",
+                    generator=torch.Generator("cuda:0").manual_seed(6))
+
+    def loss(w):
+        y = fc_tx(plan, x, w)
+        return float((y.to(torch.complex128) - t.to(torch.complex128)).abs().pow(2).sum())
+
+    w = w0.clone().requires_grad_(True)
+    J = (fc_tx(plan, x, w) - t).abs().pow(2).sum()
+    J.backward()
+    gw = w.grad.cpu().numpy().astype(np.float64)
+    h = 1e-3
+    for p in np.argsort(-np.abs(gw))[:6]:
+        e = torch.zeros_like(w0)
+        e[p] = h
+        fd = (loss(w0 + e) - loss(w0 - e)) / (2 * h)
+        print("bin %d: analytic %.6g fd %.6g" % (p, gw[p], fd), flush=True)
+        assert abs(fd - gw[p]) <= 1e-3 * abs(gw[p])

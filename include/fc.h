@@ -198,13 +198,24 @@ fc_status fc_rx_analyze(fc_plan* plan, const void* highrate_in, void* lowrate_ou
 fc_status fc_tx_adjoint(fc_plan* plan, const void* highrate_in, void* lowrate_out, void* stream);
 
 /*
- * Gradient of Re<g, tx(x)> with respect to every subband's weights:
- * grad_w[k] for k in [0, sum_m n_short_m) (subbands concatenated in plan order,
- * fftshifted order within a subband) is overwritten with
- * sum over blocks of Re(conj(G_q) * phase * X_p) for the bin p of weight k,
- * where X is the block's short FFT and G the long FFT of the matching block of
- * grad_out. lowrate_in is the forward input, grad_out the high-rate gradient
- * (both device, plan layouts); grad_w is a device float array.
+ * Gradient of the real functional J = Re<g, tx(x)> with respect to every
+ * subband's real weights D (Sec. III: the output is linear in D, so
+ * dJ/dD_p = Re<g, b_p> with b_p the output for a unit weight at bin p; this
+ * is also the weight gradient of any real loss whose complex output gradient,
+ * in PyTorch's conjugate-Wirtinger convention, is g).
+ *   lowrate_in  device, FC_OP_TX low-rate layout, the plan's I/O type: the
+ *               forward input x.
+ *   grad_out    device, high-rate layout (all streams), the plan's I/O type: g.
+ *   grad_w      device float array of sum_m n_short_m entries (subbands in
+ *               plan order, fftshifted order within a subband, as
+ *               fc_set_weights): overwritten with
+ *               sum over blocks of Re(conj(G_q) * phase * X_p),
+ *               X the block's short FFT of x, G the long FFT of the matching
+ *               block of g scaled like the adjoint, q = Xi(p).
+ * Buffers are owned by the caller. Asynchronous on `stream`; the result does
+ * not depend on the plan's current weights. Errors: FC_E_ARG (null pointer), FC_E_STATE
+ * (host-only plan, or a plan with an FC_SYNC_OLS subband, which has no TX),
+ * FC_E_DEVICE (launch failure).
  */
 fc_status fc_tx_weight_grad(fc_plan* plan, const void* lowrate_in, const void* grad_out,
                             float* grad_w, void* stream);
@@ -213,6 +224,51 @@ fc_status fc_tx_weight_grad(fc_plan* plan, const void* lowrate_in, const void* g
  * items) and kernel launches per call. Either pointer may be NULL. */
 fc_status fc_plan_stats(const fc_plan* plan, int32_t op, int64_t* n_blocks, int64_t* n_tasks,
                         int64_t* n_launches);
+
+/*
+ * Tuning of operation op (FC_OP_TX, FC_OP_RX, FC_OP_ADJ; FC_OP_ADJ also sets
+ * the weight gradient's work split):
+ *   run_len  FC blocks per workgroup task (consecutive blocks of one group;
+ *            0 = the planner's choice from the total block count; TX runs of
+ *            synchronised groups are rounded up to whole symbols; RX tasks
+ *            that accumulate into shared samples always hold one block);
+ *   conc     1..4: how many launches of one independent set (kernel classes
+ *            writing disjoint outputs) may run at once, on the caller's
+ *            stream plus side streams owned by the plan.
+ * Results do not depend on the tuning (same arithmetic per block).
+ * fc_plan_set_tuning waits for the plan's device to go idle and rebuilds the
+ * op's work tables. Errors: FC_E_ARG (out of range), FC_E_STATE (op not
+ * available for this plan), FC_E_NOMEM / FC_E_DEVICE.
+ */
+fc_status fc_plan_set_tuning(fc_plan* plan, int32_t op, int32_t run_len, int32_t conc);
+fc_status fc_plan_get_tuning(const fc_plan* plan, int32_t op, int32_t* run_len, int32_t* conc);
+
+/*
+ * Autotuner: times op on the caller's buffers (in / out as for the op's
+ * call; out is overwritten) for run_len in {0, 8, 16, 32, 64} (TX) or
+ * {0, 1, 2, 4, 8, 16} (RX, adjoint) and conc in {1, 4}, one warm-up and three
+ * timed calls each (HIP events on `stream`, minimum kept), then applies the
+ * fastest. Synchronous. The chosen values and time per call (ms) are written
+ * to the non-NULL result pointers.
+ */
+fc_status fc_plan_autotune(fc_plan* plan, int32_t op, const void* in, void* out, void* stream,
+                           int32_t* best_run_len, int32_t* best_conc, float* best_ms);
+
+/*
+ * HIP graphs of FC calls. fc_graph_begin starts a capture of `stream` (not
+ * the legacy null stream); every fc_* call issued on it until fc_graph_end
+ * is recorded (kernel launches, fills, fork/join of the side streams; none
+ * allocates or synchronises), and fc_graph_end instantiates the graph.
+ * fc_graph_launch replays it on any stream. Plans and buffers are recorded
+ * by address and must outlive the graph; weights changed later with
+ * fc_set_weights* are used by later replays. Errors: FC_E_ARG, FC_E_DEVICE
+ * (capture or instantiation failed, e.g. a non-capturable call in between).
+ */
+typedef struct fc_graph fc_graph;
+fc_status fc_graph_begin(void* stream);
+fc_status fc_graph_end(void* stream, fc_graph** graph);
+fc_status fc_graph_launch(fc_graph* graph, void* stream);
+void fc_graph_destroy(fc_graph* graph);
 
 /* Human-readable name of a status code (static string). */
 const char* fc_status_str(fc_status s);

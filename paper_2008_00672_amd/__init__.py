@@ -5,7 +5,7 @@ declared in include/fc.h). ``fc`` is a ctypes binding of that ABI; importing
 this package does not load the library, the first call does, and it raises if
 the library has not been built.
 """
-from .fc import (Plan, FcError, lib, CONT_OLA, CONT_OLS, SYNC_OLA, SYNC_OLS,  # noqa: F401
+from .fc import (Plan, Graph, FcError, lib, CONT_OLA, CONT_OLS, SYNC_OLA, SYNC_OLS,  # noqa: F401
                  OP_TX, OP_RX, OP_ADJ)
 
 

@@ -86,8 +86,12 @@ struct Op {
   // One kernel launch. kind: 0 = FC kernel of class cls (0 TX pruned, 1 TX
   // full, 2 RX / adjoint) and transform size `size`; 2 = zero the output
   // buffer. glds: LDS bytes of the weight-gradient kernel over the same tasks
-  // (adjoint op only).
-  struct Phase { int kind; int first, count; size_t lds; int aux; int64_t zero_n; int cls, size; size_t glds; };
+  // (adjoint op only). Consecutive launches with the same seq touch disjoint
+  // outputs and may run concurrently; cost is their estimated work.
+  struct Phase {
+    int kind; int first, count; size_t lds; int aux; int64_t zero_n; int cls, size; size_t glds;
+    int seq; double cost;
+  };
   std::vector<Phase> phases;
   // device copies
   SbDesc* d_sb = nullptr; GroupDesc* d_grp = nullptr; BlockDesc* d_blk = nullptr;
@@ -96,6 +100,8 @@ struct Op {
 };
 
 }  // namespace
+
+constexpr int kMaxConc = 4;      // user stream + three side streams
 
 struct fc_plan {
   int device = 0, io = 0;
@@ -109,6 +115,11 @@ struct fc_plan {
   Cf* d_tw = nullptr;
   Cf* d_twp = nullptr;           // per-pass twiddle bases
   Op op[3];
+  int run_len[3] = {0, 0, 0};    // blocks per task per op (0: planner heuristic)
+  int conc[3] = {kMaxConc, kMaxConc, kMaxConc};   // per op: launches of one independent set in flight
+  hipStream_t side[kMaxConc - 1] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kMaxConc - 1] = {};
 };
 
 namespace {
@@ -421,7 +432,8 @@ void build_op(fc_plan* P, int kind) {
       const bool ola = G.sync || G.ola;
       int64_t total_blocks = 0;
       for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
-      int K = (int)std::max<int64_t>(8, std::min<int64_t>(64, total_blocks / 2048));
+      int K = P->run_len[0] > 0 ? P->run_len[0]
+                                : (int)std::max<int64_t>(8, std::min<int64_t>(64, total_blocks / 2048));
       if (G.sync) K += K & 1;                           // whole symbols per run
       for (int b0 = 0; b0 < nblk; b0 += K) {
         const int b1 = std::min(nblk, b0 + K);
@@ -467,7 +479,9 @@ void build_op(fc_plan* P, int kind) {
       any_ola_rx |= acc;
       int64_t total_blocks = 0;
       for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
-      const int K = acc ? 1 : (int)std::max<int64_t>(2, std::min<int64_t>(8, total_blocks / 4096));
+      const int K = acc ? 1
+                        : P->run_len[kind] > 0 ? P->run_len[kind]
+                                               : (int)std::max<int64_t>(2, std::min<int64_t>(8, total_blocks / 4096));
       for (int b = 0; b < nblk; b += K) {
         TaskDesc t{};
         t.group = (int)g; t.blk_first = first_blk + b; t.blk_count = std::min(K, nblk - b);
@@ -481,7 +495,7 @@ void build_op(fc_plan* P, int kind) {
       }
     }
   }
-  auto emit = [&](PhaseTasks& ph, bool sort_cost) {
+  auto emit = [&](PhaseTasks& ph, bool sort_cost, int seq) {
     // largest transforms first (several launches of one phase are independent)
     std::vector<std::pair<std::tuple<int, int, int>, ClassTasks*>> order;
     for (auto& kv : ph.cls) order.push_back({kv.first, &kv.second});
@@ -502,21 +516,25 @@ void build_op(fc_plan* P, int kind) {
           return cost(a) > cost(b);
         });
       }
+      double cost = 0;
+      for (const TaskDesc& t : ct.t) cost += (double)op.grp[t.group].N * t.blk_count;
       Op::Phase p{0, (int)op.task.size(), (int)ct.t.size(), ct.lds, ct.aux, 0, std::get<0>(kv.first),
-                  std::get<1>(kv.first), ct.glds};
+                  std::get<1>(kv.first), ct.glds, seq, cost};
       op.task.insert(op.task.end(), ct.t.begin(), ct.t.end());
       op.phases.push_back(p);
     }
   };
   if (kind == 0) {
-    if (any_acc_tx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, P->hi_off.back(), 0, 0, 0});
-    for (auto& kv : tx_phase) emit(kv.second, true);
+    if (any_acc_tx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, P->hi_off.back(), 0, 0, 0, -1, 0});
+    // groups of one rank belong to different streams: their launches are independent
+    for (auto& kv : tx_phase) emit(kv.second, true, kv.first);
   } else {
-    if (any_ola_rx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, op.lo_off.back(), 0, 0, 0});
-    // RX tasks keep block order (neighbouring blocks share input in L2)
-    emit(rx_all, false);
-    emit(rx_even, false);
-    emit(rx_odd, false);
+    if (any_ola_rx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, op.lo_off.back(), 0, 0, 0, -1, 0});
+    // RX tasks keep block order (neighbouring blocks share input in L2).
+    // Accumulating tasks: even blocks, then odd ones (they share samples).
+    emit(rx_all, false, 0);
+    emit(rx_even, false, 0);
+    emit(rx_odd, false, 1);
   }
 }
 
@@ -539,6 +557,21 @@ void free_op(Op& op) {
   op.d_sb = nullptr; op.d_grp = nullptr; op.d_blk = nullptr; op.d_bsb = nullptr; op.d_task = nullptr;
 }
 
+hipError_t launch_phase(fc_plan* P, const Op& op, const Op::Phase& ph, const void* in, void* out, hipStream_t st) {
+  if (ph.kind == 2) return launch_zero(out, ph.zero_n, P->io, st);
+  LaunchArgs a{};
+  a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
+  a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
+  a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
+  a.in = in; a.out = out;
+  return launch_kernel(ph.cls, ph.size, a, ph.aux, ph.lds, st);
+}
+
+// Launches the op's phases in order. A run of phases with one seq is
+// independent work: it is spread over the caller's stream and up to
+// conc - 1 side streams (fork and join through events, so the caller's
+// stream order is kept and a graph capture of the caller's stream records
+// the branches).
 fc_status run_op(fc_plan* P, int kind, const void* in, void* out, hipStream_t st) {
   Op& op = P->op[kind];
   if (!op.valid || P->device < 0) return FC_E_STATE;
@@ -546,23 +579,32 @@ fc_status run_op(fc_plan* P, int kind, const void* in, void* out, hipStream_t st
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
   if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
-  fc_status result = FC_OK;
-  for (const Op::Phase& ph : op.phases) {
-    hipError_t e = hipSuccess;
-    if (ph.kind == 2) {
-      e = launch_zero(out, ph.zero_n, P->io, st);
+  hipError_t e = hipSuccess;
+  const size_t n = op.phases.size();
+  for (size_t i = 0; i < n && e == hipSuccess;) {
+    size_t j = i + 1;
+    while (j < n && op.phases[j].kind != 2 && op.phases[i].kind != 2 && op.phases[j].seq == op.phases[i].seq) ++j;
+    const int ways = std::min<int>(P->conc[kind], (int)(j - i));
+    if (ways <= 1) {
+      for (size_t k = i; k < j && e == hipSuccess; ++k) e = launch_phase(P, op, op.phases[k], in, out, st);
     } else {
-      LaunchArgs a{};
-      a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
-      a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
-      a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
-      a.in = in; a.out = out;
-      e = launch_kernel(ph.cls, ph.size, a, ph.aux, ph.lds, st);
+      e = hipEventRecord(P->ev_fork, st);
+      for (int q = 0; q + 1 < ways && e == hipSuccess; ++q) e = hipStreamWaitEvent(P->side[q], P->ev_fork, 0);
+      double load[kMaxConc] = {};
+      for (size_t k = i; k < j && e == hipSuccess; ++k) {
+        const int q = (int)(std::min_element(load, load + ways) - load);
+        load[q] += op.phases[k].cost;
+        e = launch_phase(P, op, op.phases[k], in, out, q == 0 ? st : P->side[q - 1]);
+      }
+      for (int q = 0; q + 1 < ways && e == hipSuccess; ++q) {
+        e = hipEventRecord(P->ev_join[q], P->side[q]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, P->ev_join[q], 0);
+      }
     }
-    if (e != hipSuccess) { result = FC_E_DEVICE; break; }
+    i = j;
   }
   if (cur != P->device) hipSetDevice(cur);
-  return result;
+  return e == hipSuccess ? FC_OK : FC_E_DEVICE;
 }
 
 // Weight gradient: zero grad_w, then the gradient kernel over the adjoint's
@@ -589,6 +631,14 @@ fc_status run_wgrad(fc_plan* P, const void* x, const void* g, float* grad_w, hip
   }
   if (cur != P->device) hipSetDevice(cur);
   return result;
+}
+
+// Rebuild one op's tables with the plan's current tuning (device work on the
+// old tables must have finished).
+fc_status rebuild_op(fc_plan* P, int kind) {
+  if (P->device >= 0) free_op(P->op[kind]);
+  build_op(P, kind);
+  return P->device >= 0 ? upload_op(P->op[kind]) : FC_OK;
 }
 
 }  // namespace
@@ -712,6 +762,12 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   for (int k = 0; k < 3; ++k)
     for (auto& ph : P->op[k].phases) lds_max = std::max(lds_max, std::max(ph.lds, ph.glds));
   if (!st && lds_max > 65536 && set_lds_limits(lds_max) != hipSuccess) st = FC_E_UNSUPPORTED;
+  // side streams (default priority) and fork/join events
+  for (int q = 0; q + 1 < kMaxConc && !st; ++q) {
+    if (hipStreamCreateWithFlags(&P->side[q], hipStreamNonBlocking) != hipSuccess) { P->side[q] = nullptr; st = FC_E_DEVICE; }
+    else if (hipEventCreateWithFlags(&P->ev_join[q], hipEventDisableTiming) != hipSuccess) { P->ev_join[q] = nullptr; st = FC_E_DEVICE; }
+  }
+  if (!st && hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess) { P->ev_fork = nullptr; st = FC_E_DEVICE; }
   hipSetDevice(cur);
   if (st) { fc_plan_destroy(P); return st; }
   *plan = P;
@@ -724,6 +780,11 @@ void fc_plan_destroy(fc_plan* P) {
   int cur = -1;
   hipGetDevice(&cur);
   hipSetDevice(P->device);
+  for (int q = 0; q + 1 < kMaxConc; ++q) {
+    if (P->side[q]) { hipStreamSynchronize(P->side[q]); hipStreamDestroy(P->side[q]); }
+    if (P->ev_join[q]) hipEventDestroy(P->ev_join[q]);
+  }
+  if (P->ev_fork) hipEventDestroy(P->ev_fork);
   for (int k = 0; k < 3; ++k) free_op(P->op[k]);
   hipFree(P->d_w);
   hipFree(P->d_tw);
@@ -805,6 +866,75 @@ fc_status fc_get_weights(const fc_plan* P, int32_t sb, float* w_host, int32_t n)
   if (e == hipSuccess) e = hipMemcpy(w_host, P->d_w + P->w_off[sb], n * sizeof(float), hipMemcpyDeviceToHost);
   if (cur != P->device) hipSetDevice(cur);
   return e == hipSuccess ? FC_OK : FC_E_DEVICE;
+}
+
+fc_status fc_plan_set_tuning(fc_plan* P, int32_t op, int32_t run_len, int32_t conc) {
+  if (!P || op < 0 || op > 2 || run_len < 0 || run_len > 256 || conc < 1 || conc > kMaxConc) return FC_E_ARG;
+  if (!P->op[op].valid) return FC_E_STATE;
+  if (P->device >= 0) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
+    const bool ok = hipDeviceSynchronize() == hipSuccess;
+    P->run_len[op] = run_len;
+    P->conc[op] = conc;
+    const fc_status st = ok ? rebuild_op(P, op) : FC_E_DEVICE;
+    hipSetDevice(cur);
+    return st;
+  }
+  P->run_len[op] = run_len;
+  P->conc[op] = conc;
+  return rebuild_op(P, op);
+}
+
+fc_status fc_plan_get_tuning(const fc_plan* P, int32_t op, int32_t* run_len, int32_t* conc) {
+  if (!P || op < 0 || op > 2) return FC_E_ARG;
+  if (run_len) *run_len = P->run_len[op];
+  if (conc) *conc = P->conc[op];
+  return FC_OK;
+}
+
+fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, void* stream, int32_t* best_run_len,
+                           int32_t* best_conc, float* best_ms) {
+  if (!P || op < 0 || op > 2 || !in || !out) return FC_E_ARG;
+  if (!P->op[op].valid || P->device < 0) return FC_E_STATE;
+  const hipStream_t st = (hipStream_t)stream;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
+  const std::vector<int> lens = op == FC_OP_TX ? std::vector<int>{0, 8, 16, 32, 64}
+                                               : std::vector<int>{0, 1, 2, 4, 8, 16};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  fc_status result = FC_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) result = FC_E_DEVICE;
+  float best = 1e30f;
+  int b_len = P->run_len[op], b_conc = P->conc[op];
+  for (int conc : {1, kMaxConc}) {
+    for (int len : lens) {
+      if (result != FC_OK) break;
+      if ((result = fc_plan_set_tuning(P, op, len, conc)) != FC_OK) break;
+      float t_min = 1e30f;
+      for (int rep = 0; rep < 4 && result == FC_OK; ++rep) {       // one warm-up, three timed calls
+        if (hipEventRecord(e0, st) != hipSuccess) { result = FC_E_DEVICE; break; }
+        if ((result = run_op(P, op, in, out, st)) != FC_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          result = FC_E_DEVICE;
+          break;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) t_min = std::min(t_min, ms);
+      }
+      if (result == FC_OK && t_min < best) { best = t_min; b_len = len; b_conc = conc; }
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipSetDevice(cur);
+  if (result != FC_OK) return result;
+  if ((result = fc_plan_set_tuning(P, op, b_len, b_conc)) != FC_OK) return result;
+  if (best_run_len) *best_run_len = b_len;
+  if (best_conc) *best_conc = b_conc;
+  if (best_ms) *best_ms = best;
+  return FC_OK;
 }
 
 fc_status fc_plan_stats(const fc_plan* P, int32_t op, int64_t* n_blocks, int64_t* n_tasks, int64_t* n_launches) {

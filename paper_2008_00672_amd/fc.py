@@ -47,6 +47,13 @@ EXPORTS = {
     "fc_rx_analyze": (_I32, [_P, _P, _P, _P]),
     "fc_tx_adjoint": (_I32, [_P, _P, _P, _P]),
     "fc_tx_weight_grad": (_I32, [_P, _P, _P, _P, _P]),
+    "fc_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
+    "fc_plan_get_tuning": (_I32, [_P, _I32, _I32P, _I32P]),
+    "fc_plan_autotune": (_I32, [_P, _I32, _P, _P, _P, _I32P, _I32P, ctypes.POINTER(ctypes.c_float)]),
+    "fc_graph_begin": (_I32, [_P]),
+    "fc_graph_end": (_I32, [_P, ctypes.POINTER(_P)]),
+    "fc_graph_launch": (_I32, [_P, _P]),
+    "fc_graph_destroy": (None, [_P]),
     "fc_status_str": (ctypes.c_char_p, [_I32]),
     "fc_version": (ctypes.c_char_p, []),
 }
@@ -249,3 +256,71 @@ class Plan:
         _check(lib().fc_tx_weight_grad(self._h, _ptr(x), _ptr(g), _ptr(out), _stream_handle(stream)),
                "fc_tx_weight_grad")
         return out
+
+    # ----------------------------------------------------------- tuning --
+    def set_tuning(self, op, run_len=0, conc=4):
+        _check(lib().fc_plan_set_tuning(self._h, op, run_len, conc), "fc_plan_set_tuning")
+
+    def get_tuning(self, op):
+        r, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fc_plan_get_tuning(self._h, op, ctypes.byref(r), ctypes.byref(c)), "fc_plan_get_tuning")
+        return dict(run_len=r.value, conc=c.value)
+
+    def autotune(self, op, inp, out, stream=None):
+        """Time the op's work splits on these buffers (out is overwritten) and
+        keep the fastest; returns the choice and its time per call."""
+        lo, hi = self.layout(op)
+        n_in, n_out = (int(lo[-1]), int(hi[-1])) if op == OP_TX else (int(hi[-1]), int(lo[-1]))
+        self._check_buf(inp, n_in, "input")
+        self._check_buf(out, n_out, "output")
+        r, c, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        _check(lib().fc_plan_autotune(self._h, op, _ptr(inp), _ptr(out), _stream_handle(stream), ctypes.byref(r),
+                                      ctypes.byref(c), ctypes.byref(ms)), "fc_plan_autotune")
+        return dict(run_len=r.value, conc=c.value, ms=ms.value)
+
+
+class Graph:
+    """A HIP graph of FC calls: ``with Graph(stream) as g: plan.tx(...)``
+    records the calls made on ``stream`` (a non-default torch stream) inside
+    the block; ``g.launch()`` replays them."""
+
+    def __init__(self, stream):
+        if stream is None or stream.cuda_stream == 0:
+            raise ValueError("capture needs a non-default stream")
+        self.stream = stream
+        self._g = None
+
+    def __enter__(self):
+        import torch
+        self._prev = torch.cuda.current_stream(self.stream.device)
+        torch.cuda.set_stream(self.stream)
+        _check(lib().fc_graph_begin(_stream_handle(self.stream)), "fc_graph_begin")
+        return self
+
+    def __exit__(self, et, ev, tb):
+        import torch
+        h = _P()
+        st = lib().fc_graph_end(_stream_handle(self.stream), ctypes.byref(h))
+        torch.cuda.set_stream(self._prev)
+        if et is None:
+            _check(st, "fc_graph_end")
+            self._g = h
+        elif h.value:
+            lib().fc_graph_destroy(h)
+        return False
+
+    def launch(self, stream=None):
+        if self._g is None:
+            raise RuntimeError("graph not captured")
+        _check(lib().fc_graph_launch(self._g, _stream_handle(stream or self.stream)), "fc_graph_launch")
+
+    def close(self):
+        if self._g is not None and _lib is not None:
+            lib().fc_graph_destroy(self._g)
+        self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -163,3 +163,37 @@ def test_sync_ols_has_no_tx():
     with pytest.raises(fc.FcError):
         p.layout(fc.OP_TX)
     p.layout(fc.OP_RX)
+
+
+def test_tuning_host_plan():
+    """Run lengths change the task split, never the blocks; bad values are rejected."""
+    fc = _lib()
+    sbs, _ = W.mixed_numerology()
+    p = _plan(sbs)
+    base = p.stats(fc.OP_TX)
+    assert p.get_tuning(fc.OP_TX) == dict(run_len=0, conc=4)
+    p.set_tuning(fc.OP_TX, run_len=2, conc=1)
+    assert p.get_tuning(fc.OP_TX) == dict(run_len=2, conc=1)
+    st = p.stats(fc.OP_TX)
+    assert st["blocks"] == base["blocks"] and st["tasks"] == base["blocks"] // 2
+    p.set_tuning(fc.OP_RX, run_len=4, conc=2)
+    assert p.stats(fc.OP_RX)["blocks"] == base["blocks"]
+    for bad in (dict(run_len=-1), dict(conc=0), dict(conc=5), dict(run_len=257)):
+        with pytest.raises(fc.FcError, match="FC_E_ARG|invalid argument"):
+            p.set_tuning(fc.OP_TX, **dict(dict(run_len=0, conc=4), **bad))
+
+
+def test_tuning_rejects_missing_op():
+    fc = _lib()
+    s = W.subband(15, 2, 96, 8, 128, 1024, 0, "sync_ols")
+    with pytest.raises(fc.FcError):
+        _plan([s]).set_tuning(fc.OP_TX, 8, 1)
+
+
+def test_graph_calls_reject_bad_arguments():
+    fc = _lib()
+    L = fc.lib()
+    assert L.fc_graph_begin(None) == -1
+    assert L.fc_graph_end(None, None) == -1
+    assert L.fc_graph_launch(None, None) == -1
+    L.fc_graph_destroy(None)

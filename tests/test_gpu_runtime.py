@@ -1,0 +1,134 @@
+"""GPU runtime features through the C ABI: tuning invariance, HIP graph
+capture and replay, the autotuner.
+
+The work split (blocks per task, concurrent launches) does not change the
+arithmetic of any block, so outputs must be bit-identical across tunings;
+graph replays must reproduce the eager call exactly, replay after replay,
+with eager work and synchronisations in between.
+"""
+import numpy as np
+import pytest
+
+from fc_cases import make_inputs, oracle_tx, stream_offsets, to_device
+from fcsynth import workloads as W
+from oracle import metrics
+from test_gpu_parity import _cat, _plan, _split
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed(io="c64"):
+    sbs, meta = W.mixed_numerology("sync_ola")
+    xs, Ds, _ = make_inputs(sbs, meta["qam"], meta["seed"], "rc")
+    p = _plan(sbs, io, Ds)
+    return sbs, xs, Ds, p
+
+
+def _batched(n=24, io="f16"):
+    sbs, meta = W.batched_carriers(n_carriers=n)
+    xs, Ds, _ = make_inputs(sbs, meta["qam"], meta["seed"], "rc")
+    return sbs, xs, Ds, _plan(sbs, io, Ds)
+
+
+@pytest.mark.parametrize("op", ["tx", "rx", "adjoint"])
+def test_tuning_is_bit_exact(op):
+    import torch
+    from paper_2008_00672_amd import OP_RX, OP_TX
+    sbs, xs, Ds, p = _batched()
+    if op == "tx":
+        inp = to_device(_cat(xs), "f16")
+        call, code = p.tx, OP_TX
+    elif op == "adjoint":
+        _, lens, _ = stream_offsets(sbs)
+        rng = np.random.default_rng(5)
+        inp = to_device(rng.standard_normal(sum(lens)) + 1j * rng.standard_normal(sum(lens)), "f16")
+        call, code = p.adjoint, 2
+    else:
+        _, lens, _ = stream_offsets(sbs)
+        rng = np.random.default_rng(3)
+        inp = to_device(rng.standard_normal(sum(lens)) + 1j * rng.standard_normal(sum(lens)), "f16")
+        call, code = p.rx, OP_RX
+    ref = call(inp).clone()
+    torch.cuda.synchronize()
+    for run_len, conc in [(2, 1), (8, 4), (16, 2), (64, 4), (0, 1)]:
+        p.set_tuning(code, run_len, conc)
+        out = call(inp)
+        torch.cuda.synchronize()
+        print("%s run_len %d conc %d: equal %s" % (op, run_len, conc, torch.equal(out, ref)), flush=True)
+        assert torch.equal(out, ref)
+
+
+def test_graph_replay_matches_eager():
+    """TX and RX of two plans captured in one graph; three replays, each
+    after eager work that clobbers the outputs, each equal to the eager call."""
+    import torch
+    from paper_2008_00672_amd import Graph, OP_RX
+    sbs, xs, Ds, p = _mixed()
+    x = to_device(_cat(xs), "c64")
+    sbs_r, _, Ds_r, pr = _batched(8, "c64")
+    _, lens, _ = stream_offsets(sbs_r)
+    rng = np.random.default_rng(4)
+    yr = to_device(rng.standard_normal(sum(lens)) + 1j * rng.standard_normal(sum(lens)), "c64")
+    y = p.tx(x)
+    z = pr.rx(yr)
+    torch.cuda.synchronize()
+    y_ref, z_ref = y.clone(), z.clone()
+    s = torch.cuda.Stream()
+    with Graph(s) as g:
+        p.tx(x, y, stream=s)
+        pr.rx(yr, z, stream=s)
+    for rep in range(3):
+        y.fill_(float("nan"))
+        z.zero_()
+        torch.cuda.synchronize()
+        g.launch()
+        s.synchronize()
+        ok = torch.equal(y, y_ref) and torch.equal(z, z_ref)
+        print("replay %d equal %s" % (rep, ok), flush=True)
+        assert ok
+        # eager work on the default stream in between
+        (y_ref * 2).sum().item()
+    g.close()
+
+
+def test_graph_sees_new_weights():
+    """Weights are read when the kernels run: a replay after fc_set_weights
+    gives the new weights' output (checked against the oracle)."""
+    import torch
+    from paper_2008_00672_amd import Graph
+    sbs, xs, Ds, p = _mixed()
+    x = to_device(_cat(xs), "c64")
+    y = p.tx(x)
+    s = torch.cuda.Stream()
+    with Graph(s) as g:
+        p.tx(x, y, stream=s)
+    rng = np.random.default_rng(9)
+    D2 = [rng.uniform(-1, 1, len(D)) for D in Ds]
+    for i, D in enumerate(D2):
+        p.set_weights(i, D)
+    g.launch()
+    s.synchronize()
+    _, lens, _ = stream_offsets(sbs)
+    got = _split(y.cpu().numpy().astype(np.complex128), np.cumsum([0] + lens))
+    ref = oracle_tx(sbs, xs, [D.astype(np.float32).astype(np.float64) for D in D2])
+    for a, b in zip(got, ref):
+        e = metrics.err_db(a, b)
+        print("graph with new weights: err %.1f dB" % e, flush=True)
+        assert e <= -100.0
+    g.close()
+
+
+def test_autotune_keeps_results():
+    import torch
+    from paper_2008_00672_amd import OP_TX
+    sbs, xs, Ds, p = _batched(48)
+    x = to_device(_cat(xs), "f16")
+    ref = p.tx(x).clone()
+    out = p.empty(ref.shape[0])
+    best = p.autotune(OP_TX, x, out)
+    print("autotune TX:", best, flush=True)
+    assert best["run_len"] in (0, 8, 16, 32, 64) and best["conc"] in (1, 4) and best["ms"] > 0
+    assert p.get_tuning(OP_TX) == dict(run_len=best["run_len"], conc=best["conc"])
+    y = p.tx(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)

@@ -224,7 +224,8 @@ constexpr int maxit() { return (((P / R) << LOGBT) + NT - 1) / NT; }
 // One Stockham pass over P-point transforms, 2^LOGBT of them interleaved
 // (element i of transform b at index i * 2^LOGBT + b), run by NT threads.
 // NS is the product of the radices of the previous passes. The first pass
-// reads through load(slot, i, b); the last hands results to store(slot, t, v).
+// reads through load(slot, i, b, ip); the last hands results to
+// store(slot, t, v, tp); ip / tp are the padded LDS positions of the element.
 template <int NT, int P, int LOGBT, int R, int NS, int DIR, bool FIRST, bool LAST, class Load, class Store>
 __device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load& load, Store& store,
                                          const TwB<R>* tb) {
@@ -234,17 +235,24 @@ __device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load
   constexpr int MAXIT = (TOTAL + NT - 1) / NT;
   static_assert(MAXIT * R <= 16, "at most 16 complex values per thread");
   float2 v[MAXIT][R];
+  // LDS offsets: element base + r * S sits at pad(base) + r * S + (r * S) / 32
+  // for every thread (base < S when S < 32; S a multiple of 32 otherwise), so
+  // each access is one per-thread base plus a compile-time offset.
+  constexpr int SR = NB * BT;            // read stride
+  constexpr int SW = NS * BT;            // write stride
 #pragma unroll
   for (int it = 0; it < MAXIT; ++it) {
     const int g = tid + it * NT;
     if (TOTAL % NT == 0 || g < TOTAL) {
       const int b = g & (BT - 1), j = g >> LOGBT;
+      if constexpr (FIRST) {
+        const int p0 = pad((j << LOGBT) + b);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if constexpr (FIRST)
-          v[it][r] = load(it * R + r, j + r * NB, b);
-        else
-          v[it][r] = buf[pad(((j + r * NB) << LOGBT) + b)];
+        for (int r = 0; r < R; ++r) v[it][r] = load(it * R + r, j + r * NB, b, p0 + r * SR + ((r * SR) >> 5));
+      } else {
+        const float2* rp = buf + pad((j << LOGBT) + b);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[it][r] = rp[r * SR + ((r * SR) >> 5)];
       }
     }
   }
@@ -258,12 +266,14 @@ __device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load
       if constexpr (!FIRST) apply_twiddles<R, DIR>(v[it], tb[it]);
       Dft<R, DIR>::run(v[it]);
       if constexpr (LAST) {
+        const int p0 = pad((j << LOGBT) + b);
 #pragma unroll
-        for (int r = 0; r < R; ++r) store(it * R + r, ((j + r * NB) << LOGBT) + b, v[it][r]);
+        for (int r = 0; r < R; ++r)
+          store(it * R + r, ((j + r * NB) << LOGBT) + b, v[it][r], p0 + r * SR + ((r * SR) >> 5));
       } else {
-        const int base = (j - k) * R + k;
+        float2* wp = buf + pad((((j - k) * R + k) << LOGBT) + b);
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[pad(((base + r * NS) << LOGBT) + b)] = v[it][r];
+        for (int r = 0; r < R; ++r) wp[r * SW + ((r * SW) >> 5)] = v[it][r];
       }
     }
   }
@@ -329,19 +339,21 @@ template <> struct Io<IO_F16> {
   static __device__ __forceinline__ float2 ld(const T* p, int i) { return __half22float2(p[i]); }
   static __device__ __forceinline__ void st(T* p, int i, float2 v) { p[i] = __float22half2_rn(v); }
 };
-__device__ __forceinline__ uint32_t f2bf_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;        // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
+// gfx950 converts a float pair to bfloat16 with round-to-nearest-even in one
+// instruction (v_cvt_pk_bf16_f32), which the __bf16 conversions select.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 template <> struct Io<IO_BF16> {
   using T = uint32_t;
   static __device__ __forceinline__ float2 ld(const T* p, int i) {
     const uint32_t u = p[i];
     return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
   }
-  static __device__ __forceinline__ void st(T* p, int i, float2 v) { p[i] = f2bf_rne(v.x) | (f2bf_rne(v.y) << 16); }
+  static __device__ __forceinline__ void st(T* p, int i, float2 v) {
+    bf16x2_t r;
+    r.x = (__bf16)v.x;
+    r.y = (__bf16)v.y;
+    p[i] = __builtin_bit_cast(uint32_t, r);
+  }
 };
 
 template <int IO>
@@ -362,7 +374,7 @@ __device__ __forceinline__ void put(typename Io<IO>::T* p, int i, float2 v, bool
 // Low-rate segment: block sample i is x[i] inside [lo, hi), else 0.
 template <int IO> struct LoadSeg : NoPrefetch {
   const typename Io<IO>::T* x; int lo, hi;
-  __device__ __forceinline__ float2 operator()(int, int i, int) const {
+  __device__ __forceinline__ float2 operator()(int, int i, int, int) const {
     return (i >= lo && i < hi) ? Io<IO>::ld(x, i) : make_float2(0.f, 0.f);
   }
 };
@@ -388,7 +400,7 @@ template <int IO, int NT, int P> struct LoadAhead : NoPrefetch {
       }
     }
   }
-  __device__ __forceinline__ float2 operator()(int slot, int, int) const {
+  __device__ __forceinline__ float2 operator()(int slot, int, int, int) const {
     return (valid >> slot) & 1u ? Io<IO>::ld(raw, slot) : make_float2(0.f, 0.f);
   }
 };
@@ -396,7 +408,7 @@ template <int IO, int NT, int P> struct LoadAhead : NoPrefetch {
 // Natural-order LDS read (first pass reading an LDS spectrum).
 struct LoadLds : NoPrefetch {
   const float2* s;
-  __device__ __forceinline__ float2 operator()(int, int i, int) const { return s[i]; }
+  __device__ __forceinline__ float2 operator()(int, int i, int, int) const { return s[i]; }
 };
 
 // TX, pruned long IFFT: short-FFT bin u -> residue rho = (u + c) mod L of the
@@ -413,7 +425,7 @@ template <int NT, int L> struct StoreBand {
       if (u >= 0) d[s] = D[(u + (L >> 1)) & (L - 1)];
     }
   }
-  __device__ __forceinline__ void operator()(int slot, int u, float2 v) const {
+  __device__ __forceinline__ void operator()(int slot, int u, float2 v, int) const {
     V[(u + c) & (L - 1)] = cscale(cmul(v, ph), d[slot]);
   }
 };
@@ -436,7 +448,7 @@ template <int NT, int L, int LOGI> struct LoadPruned {
       }
     }
   }
-  __device__ __forceinline__ float2 operator()(int slot, int rho, int) const {
+  __device__ __forceinline__ float2 operator()(int slot, int rho, int, int) const {
     return cmul(V[rho], make_float2(w[slot].x, -w[slot].y));
   }
 };
@@ -444,7 +456,7 @@ template <int NT, int L, int LOGI> struct LoadPruned {
 // TX, full long IFFT: add the weighted band into the N-bin spectrum.
 template <int N> struct StoreAddLong : NoPrefetch {
   float2* S; const float* D; float2 ph; int L, q0;
-  __device__ __forceinline__ void operator()(int, int u, float2 v) const {
+  __device__ __forceinline__ void operator()(int, int u, float2 v, int) const {
     const int p = (u + (L >> 1)) & (L - 1);
     const int q = (q0 + p) & (N - 1);
     S[q] = cadd(S[q], cscale(cmul(v, ph), D[p]));
@@ -456,7 +468,7 @@ template <int N> struct StoreAddLong : NoPrefetch {
 struct TxEpi : NoPrefetch {
   const float2* pend; int pth;
   float2 val[16];
-  __device__ __forceinline__ void operator()(int slot, int t, float2 v) {
+  __device__ __forceinline__ void operator()(int slot, int t, float2 v, int) {
     if (t < pth) v = cadd(v, pend[t]);
     val[slot] = v;
   }
@@ -470,7 +482,7 @@ struct TxEpi : NoPrefetch {
 // transform would cost 32 registers per thread and one wave per SIMD.
 struct StoreScatter : NoPrefetch {
   float2* S; const uint64_t* map;
-  __device__ __forceinline__ void operator()(int, int t, float2 v) const {
+  __device__ __forceinline__ void operator()(int, int t, float2 v, int) const {
     const uint64_t e = map[t];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -484,7 +496,7 @@ struct StoreScatter : NoPrefetch {
 // High-rate segment with an input window [lo, hi).
 template <int IO> struct LoadHigh : NoPrefetch {
   const typename Io<IO>::T* x; int lo, hi;
-  __device__ __forceinline__ float2 operator()(int, int i, int) const {
+  __device__ __forceinline__ float2 operator()(int, int i, int, int) const {
     return (i >= lo && i < hi) ? Io<IO>::ld(x, i) : make_float2(0.f, 0.f);
   }
 };
@@ -503,15 +515,15 @@ template <int NT, int L> struct LoadCompact {
       if (first_pos<NT, L, 0>(s, tid, u, b)) d[s] = D[(u + (L >> 1)) & (L - 1)];
     }
   }
-  __device__ __forceinline__ float2 operator()(int slot, int u, int) const {
-    return cscale(cmul(R[pad(u)], ph), d[slot]);
+  __device__ __forceinline__ float2 operator()(int slot, int, int, int up) const {
+    return cscale(cmul(R[up], ph), d[slot]);
   }
 };
 
 // RX output: keep window [lo, hi) of the low-rate block.
 template <int IO> struct StoreLow : NoPrefetch {
   typename Io<IO>::T* out; int lo, hi; bool acc;
-  __device__ __forceinline__ void operator()(int, int i, float2 v) const {
+  __device__ __forceinline__ void operator()(int, int i, float2 v, int) const {
     if (i >= lo && i < hi) put<IO>(out, i, v, acc);
   }
 };
@@ -772,8 +784,8 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int) {
 // subband's region) and X the forward short-FFT bin.
 struct StoreGrad : NoPrefetch {
   const float2* R; float2 ph; float* acc;
-  __device__ __forceinline__ void operator()(int, int u, float2 x) const {
-    const float2 a = cmul(R[pad(u)], ph);
+  __device__ __forceinline__ void operator()(int, int u, float2 x, int up) const {
+    const float2 a = cmul(R[up], ph);
     acc[u] += a.x * x.x + a.y * x.y;
   }
 };

@@ -571,17 +571,21 @@ __device__ __forceinline__ void zero_span(void* out, int64_t lo, int64_t hi) {
   for (int i = threadIdx.x; i < n; i += kThreads) Io<IO>::st(p, i, make_float2(0.f, 0.f));
 }
 
-// Single-subband group, N = L * 2^LOGI: short FFT (one wave when L <= 1024),
-// then the long IFFT evaluated as 2^LOGI interleaved L-point IFFTs of the
-// twiddled band (outputs land in natural order).
+// Single-subband group, N = L * 2^LOGI: short FFT, then the long IFFT
+// evaluated as 2^LOGI interleaved L-point IFFTs of the twiddled band (outputs
+// land in natural order). With L <= 1024 the blocks go in groups of four:
+// each wave runs the short FFT of one block of the group into its own band
+// region, then the workgroup runs the four long IFFTs and epilogues in block
+// order (the OLA carry passes from block to block through LDS). Larger L:
+// one block at a time, the short FFT on the whole workgroup.
 template <int IO, int L, int LOGI>
 __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
   constexpr int N = L << LOGI;
-  // the short FFT runs on one wave when it fits (no workgroup barriers)
-  constexpr int NTS = L <= 1024 ? 64 : kThreads;
-  // fetching the first-pass twiddles before the short FFT keeps 32 more
-  // registers live through it; worth it only where occupancy does not drop
-  constexpr bool kEarlyTwiddles = N <= 2048;
+  constexpr bool kWaveShort = L <= 1024;
+  constexpr int NB = kWaveShort ? 4 : 1;                  // blocks per group
+  // the long IFFT's first-pass twiddles depend only on the thread and the
+  // subband: fetched once per task and kept where registers allow
+  constexpr bool kKeepTwiddles = N <= 2048;
   extern __shared__ float2 smem[];
   const int task = blockIdx.x;
   if (task >= a.n_task) return;
@@ -592,51 +596,60 @@ __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
     zero_span<IO>(a.out, T.z1_lo, T.z1_hi);
   }
   const SbDesc S = a.sb[G.sb_first];
-  float2* buf = smem;                       // short FFT, band V (first L), batched IFFT
-  float2* pend = smem + lds_elems(N);       // OLA carry, up to N/2 points
+  float2* buf = smem;                         // long IFFT (and, L > 1024, short FFT and band)
+  float2* pend = smem + lds_elems(N);         // OLA carry, up to N/2 points
+  float2* bands = pend + N / 2;               // L <= 1024: one short-FFT / band region per wave
   const float* D = a.weights + S.w_off;
   const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
   const float2* twb = reinterpret_cast<const float2*>(a.twpass);
   const int tid = threadIdx.x;
-  const bool short_wave = NTS == kThreads || tid < 64;
+  const int wave = kWaveShort ? tid >> 6 : 0;
+  const int sid = kWaveShort ? tid & 63 : tid;          // index within the short FFT's threads
+  constexpr int NTS = kWaveShort ? 64 : kThreads;
+  float2* band = kWaveShort ? bands + wave * lds_elems(L) : buf;
   int64_t prev_end = INT64_MIN;
   LoadAhead<IO, NTS, L> ld;
-  {
-    const BlockSb Z0 = a.bsb[a.blk[T.blk_first].bs];
-    if (short_wave) ld.issue(at<IO>(a.in, Z0.x0), Z0.lo, Z0.hi, tid);
+  if (wave < T.blk_count) {
+    const BlockSb Z0 = a.bsb[a.blk[T.blk_first + wave].bs];
+    ld.issue(at<IO>(a.in, Z0.x0), Z0.lo, Z0.hi, sid);
   }
-  for (int bi = 0; bi < T.blk_count; ++bi) {
-    const BlockDesc B = a.blk[T.blk_first + bi];
-    const BlockSb Z = a.bsb[B.bs];
-    const int64_t next_start =
-        (T.ola && bi + 1 < T.blk_count) ? a.blk[T.blk_first + bi + 1].t0 : INT64_MAX;
-    const TxWin w = tx_window(B, T, prev_end, next_start, N);
-    LoadPruned<kThreads, L, LOGI> lp;
-    lp.V = buf; lp.tw = tw; lp.q0 = S.q0;
-    if constexpr (kEarlyTwiddles) lp.prefetch(tid);
+  LoadPruned<kThreads, L, LOGI> lp;
+  lp.tw = tw; lp.q0 = S.q0;
+  if constexpr (kKeepTwiddles) lp.prefetch(tid);
+  for (int g0 = 0; g0 < T.blk_count; g0 += NB) {
+    const int nb = T.blk_count - g0 < NB ? T.blk_count - g0 : NB;
     __syncthreads();
-    if (short_wave) {
+    if (wave < nb) {
+      const BlockSb Zw = a.bsb[a.blk[T.blk_first + g0 + wave].bs];
       StoreBand<NTS, L> sb;
-      sb.V = buf; sb.D = D; sb.ph = make_float2(Z.ph.x, Z.ph.y); sb.c = S.c;
-      fft_run<NTS, L, 0, -1>(buf, tid, ld, sb, twb);
+      sb.V = band; sb.D = D; sb.ph = make_float2(Zw.ph.x, Zw.ph.y); sb.c = S.c;
+      fft_run<NTS, L, 0, -1>(band, sid, ld, sb, twb);
     }
-    // start loading the next block's input while this block's IFFT runs
-    if (bi + 1 < T.blk_count && short_wave) {
-      const BlockSb Zn = a.bsb[a.blk[T.blk_first + bi + 1].bs];
-      ld.issue(at<IO>(a.in, Zn.x0), Zn.lo, Zn.hi, tid);
+    // start loading the next group's inputs while this group's IFFTs run
+    if (g0 + NB + wave < T.blk_count) {
+      const BlockSb Zn = a.bsb[a.blk[T.blk_first + g0 + NB + wave].bs];
+      ld.issue(at<IO>(a.in, Zn.x0), Zn.lo, Zn.hi, sid);
     }
-    __syncthreads();
-    TxEpi ep;
-    ep.pend = pend; ep.pth = w.pth;
-    if constexpr (kEarlyTwiddles) {
-      NoPrefetchWrap<LoadPruned<kThreads, L, LOGI>> lpw{lp};
-      fft_run<kThreads, L, LOGI, +1>(buf, tid, lpw, ep, twb);
-    } else {
-      fft_run<kThreads, L, LOGI, +1>(buf, tid, lp, ep, twb);
+    for (int k = 0; k < nb; ++k) {
+      const int bi = g0 + k;
+      const BlockDesc B = a.blk[T.blk_first + bi];
+      const int64_t next_start =
+          (T.ola && bi + 1 < T.blk_count) ? a.blk[T.blk_first + bi + 1].t0 : INT64_MAX;
+      const TxWin w = tx_window(B, T, prev_end, next_start, N);
+      lp.V = kWaveShort ? bands + k * lds_elems(L) : buf;
+      __syncthreads();
+      TxEpi ep;
+      ep.pend = pend; ep.pth = w.pth;
+      if constexpr (kKeepTwiddles) {
+        NoPrefetchWrap<LoadPruned<kThreads, L, LOGI>> lpw{lp};
+        fft_run<kThreads, L, LOGI, +1>(buf, tid, lpw, ep, twb);
+      } else {
+        fft_run<kThreads, L, LOGI, +1>(buf, tid, lp, ep, twb);
+      }
+      __syncthreads();
+      tx_epilogue<IO, kThreads, L, LOGI>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0);
+      prev_end = T.ola ? B.t0 + N : INT64_MIN;
     }
-    __syncthreads();
-    tx_epilogue<IO, kThreads, L, LOGI>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0);
-    prev_end = T.ola ? B.t0 + N : INT64_MIN;
   }
 }
 

@@ -464,7 +464,9 @@ void build_op(fc_plan* P, int kind) {
         ct.t.push_back(t);
         if (gd.prune) {
           ct.aux = ilog2(s0.I);
-          ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + N / 2) * 8);
+          // long IFFT buffer, OLA carry, and (L <= 1024) four short-FFT / band regions
+          const int nbands = s0.L <= 1024 ? 4 : 0;
+          ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + N / 2 + nbands * lds_elems(s0.L)) * 8);
         } else {
           ct.aux = std::max(ct.aux, lmax);
           ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + lds_elems(ct.aux) + N / 2) * 8);

@@ -170,21 +170,31 @@ def cpu_baseline(budget_s, tx_sbs, tx_meta, gpu_tx_out, tx_plan_one, rx_sbs, rx_
     """Time the FP64 oracle on a bounded sample of the same work and check the
     GPU outputs on that sample (EVM against the oracle on unquantised input)."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from fc_cases import oracle_rx, oracle_tx
+    from fc_cases import make_inputs, oracle_rx, oracle_tx, rx_frame_input, stream_offsets
     from oracle import metrics
+    from oracle.weights import rc_weights
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count()
-    xs = tx_input(tx_plan_one, tx_sbs, tx_meta)
+    # the oracle's inputs come from the same seeded generators, with the CP
+    # schedule from the oracle's own numerology; they must equal what the GPU
+    # was given (built from the library's schedule)
+    xs = make_inputs(tx_sbs, tx_meta["qam"], tx_meta["seed"], "rc")[0]
+    xs_gpu = tx_input(tx_plan_one, tx_sbs, tx_meta)
+    if not all(np.array_equal(a, b) for a, b in zip(xs, xs_gpu)):
+        raise RuntimeError("TX inputs differ between the oracle's and the library's CP schedule")
+    rx_ref_in = rx_frame_input(rx_sbs, rx_meta["qam"], rx_meta["seed"], rx_meta["snr_db"])
+    if not np.array_equal(rx_ref_in, rx_in):
+        raise RuntimeError("RX input differs between the oracle's and the library's CP schedule")
     lo, hi = tx_plan_one.layout(0)
     t0 = time.time()
     n_done, samples, evm_tx = 0, 0, []
     order = np.argsort([s["n_long"] for s in tx_sbs])      # cheap carriers first
     for k in order:
         s = dict(tx_sbs[k], stream=0)
-        ref = oracle_tx([s], [xs[k]], [tx_plan_one.get_weights(k)])[0]
+        ref = oracle_tx([s], [xs[k]], [rc_weights(s["n_short"], s["n_active"], s["n_tb"])])[0]
         got = gpu_tx_out[hi[k]:hi[k + 1]]
         evm_tx.append(metrics.err_db(got, ref))
         samples += len(ref)
@@ -196,11 +206,9 @@ def cpu_baseline(budget_s, tx_sbs, tx_meta, gpu_tx_out, tx_plan_one, rx_sbs, rx_
     t1 = time.time()
     B = 14
     sub = [dict(s, n_symbols=B) for s in rx_sbs]
-    from paper_2008_00672_amd import Plan
-    ph = Plan(sub, io="c64", device=-1)
-    _, hh = ph.layout(1)
-    seg = rx_in[:int(hh[-1])]
-    refs = oracle_rx(sub, [seg], [rx_plan_one.get_weights(i) for i in range(len(rx_sbs))])
+    _, lens_sub, _ = stream_offsets(sub)
+    seg = rx_ref_in[:lens_sub[0]]
+    refs = oracle_rx(sub, [seg], [rc_weights(s["n_short"], s["n_active"], s["n_tb"]) for s in rx_sbs])
     lo_rx, _ = rx_plan_one.layout(1)
     evm_rx = []
     for i, r in enumerate(refs):

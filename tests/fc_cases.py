@@ -104,6 +104,26 @@ def oracle_adj(subbands, streams, Ds):
     return outs
 
 
+def rx_frame_input(subbands, qam_order, seed, snr_db):
+    """One received frame for subbands sharing one stream and N: the
+    subbands' QAM CP-OFDM from one N-point IDFT per symbol (NR CP from the
+    oracle's numerology), placed so that the first symbol's useful part starts
+    N/4 into the stream (the synchronised receiver's first block), plus AWGN
+    at the given SNR over the signal power."""
+    rng = np.random.default_rng(seed)
+    P = [sub_params(s) for s in subbands]
+    ncp = P[0]["ncp"]
+    grids = [fcsynth.qam_grid(rng, qam_order, s["n_symbols"], s["n_active"]) for s in subbands]
+    N = subbands[0]["n_long"]
+    sig = fcsynth.cp_ofdm_highrate(grids, [s["center_bin"] for s in subbands], N, ncp)
+    _, lens, _ = stream_offsets(subbands)
+    y = np.zeros(lens[0], dtype=complex)
+    lead = N // 4 - ncp[0]
+    y[lead:lead + len(sig)] = sig
+    y += fcsynth.awgn(rng, lens[0], np.mean(np.abs(sig) ** 2) * 10 ** (-snr_db / 10))
+    return y
+
+
 def subband_forward(subband, x):
     """D -> this subband's FC output (oracle), with its input x fixed."""
     p = sub_params(subband)

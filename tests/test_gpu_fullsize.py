@@ -1,0 +1,78 @@
+"""Parity at the benchmark's full sizes, in the launch configuration that
+bench.py times (autotuned work split), on outputs the oracle can compute one
+piece at a time.
+
+TX: 256 uneven carriers x 32 slot-batches (8192 streams), FP16 I/Q; sampled
+carriers of sampled batches against the oracle (FP16 gate -60 dB).
+RX: 8 subbands of a 100 MHz carrier x 100 frames, BF16 I/Q; the first 14
+symbols of sampled frames against the oracle (BF16 gate -50 dB).
+"""
+import numpy as np
+import pytest
+
+from fc_cases import GATE_DB, from_device, make_inputs, oracle_rx, oracle_tx, rx_frame_input, to_device
+from fcsynth import workloads as W
+from oracle import metrics
+from oracle import weights as ow
+
+pytestmark = pytest.mark.gpu
+
+TX_BATCHES = 32
+RX_FRAMES = 100
+
+
+def test_batched_tx_full_size():
+    import torch
+    from paper_2008_00672_amd import OP_TX, Plan
+    sbs, meta = W.batched_carriers()
+    allsb = [dict(s, stream=b * len(sbs) + k) for b in range(TX_BATCHES) for k, s in enumerate(sbs)]
+    p = Plan(allsb, io="f16", device=0)
+    xs, _, _ = make_inputs(sbs, meta["qam"], meta["seed"], "rc")
+    x1 = to_device(np.concatenate(xs), "f16")
+    x = x1.repeat(TX_BATCHES, 1).contiguous()
+    lo, hi = p.layout(OP_TX)
+    assert x.shape[0] == lo[-1]
+    y = p.empty(int(hi[-1]))
+    tune = p.autotune(OP_TX, x, y)
+    print("TX autotune:", tune, flush=True)
+    y = p.tx(x, y)
+    torch.cuda.synchronize()
+    for b in (0, 13, TX_BATCHES - 1):
+        for k in (0, 1, 2, 77, 128, 200, 255):
+            j = b * len(sbs) + k
+            got = from_device(y[int(hi[j]):int(hi[j + 1])], "f16")
+            s = dict(sbs[k], stream=0)
+            ref = oracle_tx([s], [xs[k]], [ow.rc_weights(s["n_short"], s["n_active"], s["n_tb"])])[0]
+            e = metrics.err_db(got, ref)
+            print("batch %d carrier %d (L %d N %d): err %.1f dB" % (b, k, s["n_short"], s["n_long"], e), flush=True)
+            assert e <= GATE_DB["f16"]
+
+
+def test_rx_filterbank_full_size():
+    import torch
+    from paper_2008_00672_amd import OP_RX, Plan
+    sbs, meta = W.rx_filterbank()
+    allsb = [dict(s, stream=f) for f in range(RX_FRAMES) for s in sbs]
+    p = Plan(allsb, io="bf16", device=0)
+    y1 = rx_frame_input(sbs, meta["qam"], meta["seed"], meta["snr_db"])
+    lo, hi = p.layout(OP_RX)
+    assert len(y1) == hi[1] - hi[0]
+    r = to_device(y1, "bf16").repeat(RX_FRAMES, 1).contiguous()
+    z = p.empty(int(lo[-1]))
+    tune = p.autotune(OP_RX, r, z)
+    print("RX autotune:", tune, flush=True)
+    z = p.rx(r, z)
+    torch.cuda.synchronize()
+    B = 14
+    sub = [dict(s, n_symbols=B) for s in sbs]
+    from fc_cases import stream_offsets
+    _, lens, _ = stream_offsets(sub)
+    Ds = [ow.rc_weights(s["n_short"], s["n_active"], s["n_tb"]) for s in sbs]
+    refs = oracle_rx(sub, [y1[:lens[0]]], Ds)
+    for f in (0, 41, RX_FRAMES - 1):
+        for m, ref in enumerate(refs):
+            j = f * len(sbs) + m
+            got = from_device(z[int(lo[j]):int(lo[j]) + len(ref)], "bf16")
+            e = metrics.err_db(got, ref)
+            print("frame %d subband %d (L %d): err %.1f dB" % (f, m, sbs[m]["n_short"], e), flush=True)
+            assert e <= GATE_DB["bf16"]

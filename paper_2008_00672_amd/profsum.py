@@ -46,7 +46,8 @@ def stats_md(path, out, command):
             tx_avg += avg
         lines.append("| %s | %s | %.1f | %.2f | %.1f |" % (k, r["Calls"], avg, float(r["TotalDurationNs"]) / 1e6,
                                                           float(r["Percentage"])))
-    lines += ["", "Sum of the fc_tx_* class averages (one TX call): %.1f us" % tx_avg, ""]
+    lines += ["", "Sum of the fc_tx_* class averages: %.1f us (the TX classes of one call run concurrently on "
+              "side streams, so this exceeds the call's wall time, which bench.py measures)." % tx_avg, ""]
     open(out, "w").write("\n".join(lines))
 
 
@@ -84,8 +85,29 @@ def traffic(op, fetch, write, cfetch, cwrite, calls, out, command):
     return d
 
 
+def traffic_md(jsons, out, commands):
+    """Markdown table of the traffic summaries (one per op)."""
+    ds = [json.load(open(j)) for j in jsons]
+    lines = ["# HBM traffic per call (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
+             "Counter runs (repo root, MI355X), one counter per run:", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", "Calibration: a plain 256 MiB device copy under the same counters gives the scale factors "
+                  "FETCH x%.4f, WRITE x%.4f (known bytes / counter reading)." % (ds[0]["copy_factor_fetch"],
+                                                                                  ds[0]["copy_factor_write"]), "",
+              "| op | dispatches per call | FETCH KiB/call | WRITE KiB/call | calibrated HBM bytes/call |",
+              "|---|---|---|---|---|"]
+    for d in ds:
+        lines.append("| %s | %d | %.0f | %.0f | %.4g |" % (d["op"], d["dispatches"][0] // d["calls"],
+                                                          d["fetch_kib_per_call"], d["write_kib_per_call"],
+                                                          d["bytes_per_launch"]))
+    lines += ["", "Kernel source hash: %s" % ds[0]["kernel_hash"], ""]
+    open(out, "w").write("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats_md(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic_md":
+        traffic_md(sys.argv[2].split(","), sys.argv[3], sys.argv[4:])
     elif sys.argv[1] == "traffic":
         print(traffic(sys.argv[2], *sys.argv[3:7], int(sys.argv[7]), sys.argv[8], sys.argv[9]))

@@ -719,7 +719,7 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
 // planner chose, longer ones on the whole workgroup. The next block's input
 // is loaded into registers while the subbands run.
 template <int IO, int NL>
-__global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int) {
+__global__ __launch_bounds__(kThreads, 4) void fc_rx_kernel(LaunchArgs a, int) {
   extern __shared__ float2 smem[];
   // consecutive tasks (runs sharing input at their boundary) go to the same
   // XCD: the dispatcher places workgroup i on XCD i mod 8
@@ -730,7 +730,11 @@ __global__ __launch_bounds__(kThreads) void fc_rx_kernel(LaunchArgs a, int) {
   const TaskDesc T = a.task[task];
   const GroupDesc G = a.grp[T.group];
   float2* S = smem;                                        // long spectrum, then subband regions
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the planner's per-wave subband loads differ; rotating them with the
+  // workgroup index keeps the heaviest from landing on the same SIMD in every
+  // workgroup (the waves of a workgroup are spread over the CU's SIMDs in order)
+  const int wave = ((tid >> 6) + blockIdx.x) & 3;
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const uint64_t* map = a.rxmap + G.map_off;
   LoadAhead<IO, kThreads, NL> lh;
@@ -821,7 +825,11 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
   float2* S = smem;
   float2* scr = smem + G.scr_off;
   float* acc = reinterpret_cast<float*>(smem + G.acc_off);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the planner's per-wave subband loads differ; rotating them with the
+  // workgroup index keeps the heaviest from landing on the same SIMD in every
+  // workgroup (the waves of a workgroup are spread over the CU's SIMDs in order)
+  const int wave = ((tid >> 6) + blockIdx.x) & 3;
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const uint64_t* map = a.rxmap + G.map_off;
   for (int i = tid; i < G.acc_len; i += kThreads) acc[i] = 0.f;

@@ -33,7 +33,7 @@ fc_status fc_graph_end(void* stream, fc_graph** out) {
     return FC_E_DEVICE;
   }
   if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
-    hipGraphDestroy(g->graph);
+    (void)hipGraphDestroy(g->graph);
     delete g;
     return FC_E_DEVICE;
   }
@@ -48,8 +48,8 @@ fc_status fc_graph_launch(fc_graph* g, void* stream) {
 
 void fc_graph_destroy(fc_graph* g) {
   if (!g) return;
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
 }
 

@@ -19,7 +19,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/fc.h"
+#include "fc.h"
 #include "fc_internal.h"
 
 namespace fcx {

@@ -248,8 +248,11 @@ fc_status fc_plan_get_tuning(const fc_plan* plan, int32_t op, int32_t* run_len, 
  * call; out is overwritten) for run_len in {0, 8, 16, 32, 64} (TX) or
  * {0, 1, 2, 4, 8, 16} (RX, adjoint) and conc in {1, 4}, one warm-up and three
  * timed calls each (HIP events on `stream`, minimum kept), then applies the
- * fastest. Synchronous. The chosen values and time per call (ms) are written
- * to the non-NULL result pointers.
+ * fastest. With conc > 1 it first times every kernel launch of the op on its
+ * own and spreads the launches over the streams longest first by those
+ * measured times (kept until the next fc_plan_set_tuning). Synchronous. The
+ * chosen values and time per call (ms) are written to the non-NULL result
+ * pointers.
  */
 fc_status fc_plan_autotune(fc_plan* plan, int32_t op, const void* in, void* out, void* stream,
                            int32_t* best_run_len, int32_t* best_conc, float* best_ms);

@@ -553,10 +553,10 @@ __device__ __forceinline__ TxWin tx_window(const BlockDesc& B, const TaskDesc& T
 // Epilogue phase 2 (after a barrier): OLA carry-out or write the owned samples.
 template <int IO, int NT, int P, int LOGBT>
 __device__ __forceinline__ void tx_epilogue(const TxEpi& ep, float2* pend, const TxWin& w,
-                                            typename Io<IO>::T* ob, bool acc) {
+                                            typename Io<IO>::T* ob, bool acc, int tid) {
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    const int t = last_pos<NT, P, LOGBT>(s, threadIdx.x);
+    const int t = last_pos<NT, P, LOGBT>(s, tid);
     if (t < 0) continue;
     if (t >= w.cth) pend[t - w.cth] = ep.val[s];
     else if (t >= w.wlo && t < w.whi) put<IO>(ob, t, ep.val[s], acc);
@@ -573,19 +573,20 @@ __device__ __forceinline__ void zero_span(void* out, int64_t lo, int64_t hi) {
 
 // Single-subband group, N = L * 2^LOGI: short FFT, then the long IFFT
 // evaluated as 2^LOGI interleaved L-point IFFTs of the twiddled band (outputs
-// land in natural order). With L <= 1024 the blocks go in groups of four:
-// each wave runs the short FFT of one block of the group into its own band
-// region, then the workgroup runs the four long IFFTs and epilogues in block
-// order (the OLA carry passes from block to block through LDS). Larger L:
-// one block at a time, the short FFT on the whole workgroup.
+// land in natural order). With L <= 1024 the blocks go in groups of up to
+// four: each wave runs the short FFT of one block of the group into its own
+// band region, then the workgroup runs the group's long IFFTs and epilogues
+// in block order (the OLA carry passes from block to block through LDS).
+// Larger L: one block at a time, the short FFT on the whole workgroup.
 template <int IO, int L, int LOGI>
-__global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
+__global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void fc_tx_pruned_kernel(LaunchArgs a) {
   constexpr int N = L << LOGI;
   constexpr bool kWaveShort = L <= 1024;
-  constexpr int NB = kWaveShort ? 4 : 1;                  // blocks per group
+  constexpr int NB = pruned_group_blocks(L, N);             // blocks per group
   // the long IFFT's first-pass twiddles depend only on the thread and the
-  // subband: fetched once per task and kept where registers allow
-  constexpr bool kKeepTwiddles = N <= 2048;
+  // subband: fetched once per task and kept in registers where the LDS
+  // already limits occupancy to two workgroups per CU (registers are free)
+  constexpr bool kKeepTwiddles = N <= 2048 && pruned_waves_per_simd(L, N) <= 2;
   extern __shared__ float2 smem[];
   const int task = blockIdx.x;
   if (task >= a.n_task) return;
@@ -603,19 +604,24 @@ __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
   const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
   const float2* twb = reinterpret_cast<const float2*>(a.twpass);
   const int tid = threadIdx.x;
-  const int wave = kWaveShort ? tid >> 6 : 0;
+  const int wave = kWaveShort ? tid >> 6 : 0;             // waves >= NB idle in the short phase
+  // below N = 4096 the long IFFT's radix-16 passes keep N/16 threads busy:
+  // rotating the thread roles with the workgroup index spreads those threads'
+  // waves over the CU's SIMDs instead of loading the first SIMD(s) in every
+  // workgroup
+  const int rtid = (tid + 64 * (int)(blockIdx.x & 3)) & (kThreads - 1);
   const int sid = kWaveShort ? tid & 63 : tid;          // index within the short FFT's threads
   constexpr int NTS = kWaveShort ? 64 : kThreads;
   float2* band = kWaveShort ? bands + wave * lds_elems(L) : buf;
   int64_t prev_end = INT64_MIN;
   LoadAhead<IO, NTS, L> ld;
-  if (wave < T.blk_count) {
+  if (wave < NB && wave < T.blk_count) {
     const BlockSb Z0 = a.bsb[a.blk[T.blk_first + wave].bs];
     ld.issue(at<IO>(a.in, Z0.x0), Z0.lo, Z0.hi, sid);
   }
   LoadPruned<kThreads, L, LOGI> lp;
   lp.tw = tw; lp.q0 = S.q0;
-  if constexpr (kKeepTwiddles) lp.prefetch(tid);
+  if constexpr (kKeepTwiddles) lp.prefetch(rtid);
   for (int g0 = 0; g0 < T.blk_count; g0 += NB) {
     const int nb = T.blk_count - g0 < NB ? T.blk_count - g0 : NB;
     __syncthreads();
@@ -626,7 +632,7 @@ __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
       fft_run<NTS, L, 0, -1>(band, sid, ld, sb, twb);
     }
     // start loading the next group's inputs while this group's IFFTs run
-    if (g0 + NB + wave < T.blk_count) {
+    if (wave < NB && g0 + NB + wave < T.blk_count) {
       const BlockSb Zn = a.bsb[a.blk[T.blk_first + g0 + NB + wave].bs];
       ld.issue(at<IO>(a.in, Zn.x0), Zn.lo, Zn.hi, sid);
     }
@@ -642,12 +648,12 @@ __global__ __launch_bounds__(kThreads) void fc_tx_pruned_kernel(LaunchArgs a) {
       ep.pend = pend; ep.pth = w.pth;
       if constexpr (kKeepTwiddles) {
         NoPrefetchWrap<LoadPruned<kThreads, L, LOGI>> lpw{lp};
-        fft_run<kThreads, L, LOGI, +1>(buf, tid, lpw, ep, twb);
+        fft_run<kThreads, L, LOGI, +1>(buf, rtid, lpw, ep, twb);
       } else {
-        fft_run<kThreads, L, LOGI, +1>(buf, tid, lp, ep, twb);
+        fft_run<kThreads, L, LOGI, +1>(buf, rtid, lp, ep, twb);
       }
       __syncthreads();
-      tx_epilogue<IO, kThreads, L, LOGI>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0);
+      tx_epilogue<IO, kThreads, L, LOGI>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0, rtid);
       prev_end = T.ola ? B.t0 + N : INT64_MIN;
     }
   }
@@ -706,7 +712,7 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
     ep.pend = pend; ep.pth = w.pth;
     fft_run<kThreads, NL, 0, +1>(S, tid, ls, ep, tw);
     __syncthreads();
-    tx_epilogue<IO, kThreads, NL, 0>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0);
+    tx_epilogue<IO, kThreads, NL, 0>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0, (int)threadIdx.x);
     prev_end = T.ola ? B.t0 + NL : INT64_MIN;
   }
 }

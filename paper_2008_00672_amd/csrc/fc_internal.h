@@ -18,6 +18,25 @@ enum IoType : int32_t { IO_C64 = 0, IO_F16 = 1, IO_BF16 = 2 };
 // the device code's pad()).
 constexpr int lds_elems(int n) { return n + (n >> 5); }
 
+// TX pruned kernel, L <= 1024: blocks whose short FFTs run at once (one per
+// wave), the most of {4, 2, 1} whose LDS (long IFFT buffer, OLA carry, one
+// band region per block) still lets two workgroups share a CU.
+constexpr int pruned_lds_entries(int L, int N, int nb) { return lds_elems(N) + N / 2 + nb * lds_elems(L); }
+constexpr int pruned_group_blocks(int L, int N) {
+  return L > 1024 ? 1
+         : pruned_lds_entries(L, N, 4) * 8 <= 80 * 1024 ? 4
+         : pruned_lds_entries(L, N, 2) * 8 <= 80 * 1024 ? 2 : 1;
+}
+constexpr int pruned_lds_bytes(int L, int N) {
+  return pruned_lds_entries(L, N, L <= 1024 ? pruned_group_blocks(L, N) : 0) * 8;
+}
+// Workgroups per CU that the LDS allows (160 KiB per CU), at most three: the
+// register budget follows, so that registers do not lower the occupancy the
+// LDS allows, without forcing spills where LDS would allow four.
+constexpr int pruned_waves_per_simd(int L, int N) {
+  return 163840 / pruned_lds_bytes(L, N) >= 3 ? 3 : 163840 / pruned_lds_bytes(L, N);
+}
+
 struct Cf {   // complex float with the same layout as HIP's float2
   float x, y;
 };

@@ -464,9 +464,8 @@ void build_op(fc_plan* P, int kind) {
         ct.t.push_back(t);
         if (gd.prune) {
           ct.aux = ilog2(s0.I);
-          // long IFFT buffer, OLA carry, and (L <= 1024) four short-FFT / band regions
-          const int nbands = s0.L <= 1024 ? 4 : 0;
-          ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + N / 2 + nbands * lds_elems(s0.L)) * 8);
+          // long IFFT buffer, OLA carry, and (L <= 1024) the short-FFT / band regions
+          ct.lds = std::max(ct.lds, (size_t)pruned_lds_bytes(s0.L, N));
         } else {
           ct.aux = std::max(ct.aux, lmax);
           ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + lds_elems(ct.aux) + N / 2) * 8);
@@ -553,8 +552,8 @@ fc_status upload_op(Op& op) {
 }
 
 void free_op(Op& op) {
-  hipFree(op.d_sb); hipFree(op.d_grp); hipFree(op.d_blk); hipFree(op.d_bsb); hipFree(op.d_task);
-  hipFree(op.d_rxmap);
+  (void)hipFree(op.d_sb); (void)hipFree(op.d_grp); (void)hipFree(op.d_blk); (void)hipFree(op.d_bsb); (void)hipFree(op.d_task);
+  (void)hipFree(op.d_rxmap);
   op.d_rxmap = nullptr;
   op.d_sb = nullptr; op.d_grp = nullptr; op.d_blk = nullptr; op.d_bsb = nullptr; op.d_task = nullptr;
 }
@@ -605,7 +604,7 @@ fc_status run_op(fc_plan* P, int kind, const void* in, void* out, hipStream_t st
     }
     i = j;
   }
-  if (cur != P->device) hipSetDevice(cur);
+  if (cur != P->device) (void)hipSetDevice(cur);
   return e == hipSuccess ? FC_OK : FC_E_DEVICE;
 }
 
@@ -631,8 +630,41 @@ fc_status run_wgrad(fc_plan* P, const void* x, const void* g, float* grad_w, hip
     a.in = g; a.out = grad_w; a.in2 = x;
     if (launch_kernel(3, ph.size, a, ph.aux, ph.glds, st) != hipSuccess) result = FC_E_DEVICE;
   }
-  if (cur != P->device) hipSetDevice(cur);
+  if (cur != P->device) (void)hipSetDevice(cur);
   return result;
+}
+
+// Measured schedule: times every kernel launch of the op on its own (one
+// warm-up, minimum of two), stores the times as the launches' costs and
+// orders each independent set by decreasing cost, so that run_op's greedy
+// spread over the streams is the longest-processing-time-first rule on
+// measured rather than estimated work.
+fc_status measure_costs(fc_plan* P, int kind, const void* in, void* out, hipStream_t st, hipEvent_t e0,
+                        hipEvent_t e1) {
+  Op& op = P->op[kind];
+  for (Op::Phase& ph : op.phases) {
+    if (ph.kind == 2) continue;
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess || launch_phase(P, op, ph, in, out, st) != hipSuccess ||
+          hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return FC_E_DEVICE;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return FC_E_DEVICE;
+      if (rep > 0) best = std::min(best, ms);
+    }
+    ph.cost = best;
+  }
+  for (size_t i = 0; i < op.phases.size();) {
+    size_t j = i + 1;
+    while (j < op.phases.size() && op.phases[j].kind != 2 && op.phases[i].kind != 2 &&
+           op.phases[j].seq == op.phases[i].seq)
+      ++j;
+    std::stable_sort(op.phases.begin() + i, op.phases.begin() + j,
+                     [](const Op::Phase& a, const Op::Phase& b) { return a.cost > b.cost; });
+    i = j;
+  }
+  return FC_OK;
 }
 
 // Rebuild one op's tables with the plan's current tuning (device work on the
@@ -770,7 +802,7 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
     else if (hipEventCreateWithFlags(&P->ev_join[q], hipEventDisableTiming) != hipSuccess) { P->ev_join[q] = nullptr; st = FC_E_DEVICE; }
   }
   if (!st && hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess) { P->ev_fork = nullptr; st = FC_E_DEVICE; }
-  hipSetDevice(cur);
+  (void)hipSetDevice(cur);
   if (st) { fc_plan_destroy(P); return st; }
   *plan = P;
   return FC_OK;
@@ -780,18 +812,18 @@ void fc_plan_destroy(fc_plan* P) {
   if (!P) return;
   if (P->device < 0) { delete P; return; }
   int cur = -1;
-  hipGetDevice(&cur);
-  hipSetDevice(P->device);
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(P->device);
   for (int q = 0; q + 1 < kMaxConc; ++q) {
-    if (P->side[q]) { hipStreamSynchronize(P->side[q]); hipStreamDestroy(P->side[q]); }
-    if (P->ev_join[q]) hipEventDestroy(P->ev_join[q]);
+    if (P->side[q]) { (void)hipStreamSynchronize(P->side[q]); (void)hipStreamDestroy(P->side[q]); }
+    if (P->ev_join[q]) (void)hipEventDestroy(P->ev_join[q]);
   }
-  if (P->ev_fork) hipEventDestroy(P->ev_fork);
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   for (int k = 0; k < 3; ++k) free_op(P->op[k]);
-  hipFree(P->d_w);
-  hipFree(P->d_tw);
-  hipFree(P->d_twp);
-  if (cur >= 0) hipSetDevice(cur);
+  (void)hipFree(P->d_w);
+  (void)hipFree(P->d_tw);
+  (void)hipFree(P->d_twp);
+  if (cur >= 0) (void)hipSetDevice(cur);
   delete P;
 }
 
@@ -830,12 +862,12 @@ fc_status fc_set_weights(fc_plan* P, int32_t sb, const float* w_host, int32_t n,
   if (P->device < 0) return FC_OK;
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
-  if (cur != P->device) hipSetDevice(P->device);
+  if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
   hipError_t e = hipMemcpyAsync(P->d_w + P->w_off[sb], s.w.data(), n * sizeof(float), hipMemcpyHostToDevice,
                                 (hipStream_t)stream);
   // the plan's host copy is rewritten by the next call: wait for this copy
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
-  if (cur != P->device) hipSetDevice(cur);
+  if (cur != P->device) (void)hipSetDevice(cur);
   return e == hipSuccess ? FC_OK : FC_E_DEVICE;
 }
 
@@ -846,10 +878,10 @@ fc_status fc_set_weights_device(fc_plan* P, int32_t sb, const float* w_dev, int3
   if (n != s.L) return FC_E_SHAPE;
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
-  if (cur != P->device) hipSetDevice(P->device);
+  if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
   hipError_t e = hipMemcpyAsync(P->d_w + P->w_off[sb], w_dev, n * sizeof(float), hipMemcpyDeviceToDevice,
                                 (hipStream_t)stream);
-  if (cur != P->device) hipSetDevice(cur);
+  if (cur != P->device) (void)hipSetDevice(cur);
   return e == hipSuccess ? FC_OK : FC_E_DEVICE;
 }
 
@@ -863,10 +895,10 @@ fc_status fc_get_weights(const fc_plan* P, int32_t sb, float* w_host, int32_t n)
   }
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
-  if (cur != P->device) hipSetDevice(P->device);
+  if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
   hipError_t e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(w_host, P->d_w + P->w_off[sb], n * sizeof(float), hipMemcpyDeviceToHost);
-  if (cur != P->device) hipSetDevice(cur);
+  if (cur != P->device) (void)hipSetDevice(cur);
   return e == hipSuccess ? FC_OK : FC_E_DEVICE;
 }
 
@@ -880,7 +912,7 @@ fc_status fc_plan_set_tuning(fc_plan* P, int32_t op, int32_t run_len, int32_t co
     P->run_len[op] = run_len;
     P->conc[op] = conc;
     const fc_status st = ok ? rebuild_op(P, op) : FC_E_DEVICE;
-    hipSetDevice(cur);
+    (void)hipSetDevice(cur);
     return st;
   }
   P->run_len[op] = run_len;
@@ -913,6 +945,7 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
     for (int len : lens) {
       if (result != FC_OK) break;
       if ((result = fc_plan_set_tuning(P, op, len, conc)) != FC_OK) break;
+      if (conc > 1 && (result = measure_costs(P, op, in, out, st, e0, e1)) != FC_OK) break;
       float t_min = 1e30f;
       for (int rep = 0; rep < 4 && result == FC_OK; ++rep) {       // one warm-up, three timed calls
         if (hipEventRecord(e0, st) != hipSuccess) { result = FC_E_DEVICE; break; }
@@ -922,17 +955,18 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
           break;
         }
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
         if (rep > 0) t_min = std::min(t_min, ms);
       }
       if (result == FC_OK && t_min < best) { best = t_min; b_len = len; b_conc = conc; }
     }
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  hipSetDevice(cur);
+  if (result == FC_OK) result = fc_plan_set_tuning(P, op, b_len, b_conc);
+  if (result == FC_OK && b_conc > 1) result = measure_costs(P, op, in, out, st, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipSetDevice(cur);
   if (result != FC_OK) return result;
-  if ((result = fc_plan_set_tuning(P, op, b_len, b_conc)) != FC_OK) return result;
   if (best_run_len) *best_run_len = b_len;
   if (best_conc) *best_conc = b_conc;
   if (best_ms) *best_ms = best;

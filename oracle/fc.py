@@ -262,6 +262,61 @@ def rx_sync(yh, L, N, c, D, ncp, keep_cp=False):
     return np.stack(out)
 
 
+def rx_sync_subcarriers(yh, L, N, c, D, ncp):
+    """Symbol-synchronised RX followed by the OFDM demodulation of Sec. IV
+    (L_OFDM = L): x_hat_n = (1/sqrt(L)) W_L x_hat_OFDM,n for every symbol, the
+    direct approach (two short IFFTs and one FFT per symbol). Returns (B, L);
+    subcarrier kappa is column kappa mod L."""
+    return rx_sync(yh, L, N, c, D, ncp) @ dft_matrix(L) / np.sqrt(L)
+
+
+def rx_sync_blocks_freq(yh, L, N, c, D, ncp):
+    """The two frequency-domain FC block outputs of every symbol before the
+    short IFFT, g^(r) with z^(r) = W_L^{-1} g^(r) (Sec. IV blocks, Sec. V-A
+    notation): P^(-L/2) D M(1)^T W_N w_n^(r), times the conj phase and
+    1/sqrt(I). Returns an array (B, 2, L)."""
+    ov = Overlap(L, N, Fraction(1, 2))
+    sigma = sync_sigma(ncp, N)
+    yh = np.asarray(yh, dtype=complex)
+    if len(yh) != sync_output_len(ncp, ov):
+        raise ValueError("high-rate input must have length Q")
+    Dv = np.asarray(D, dtype=float)
+    Gf = (shift_matrix(L).T * Dv[None, :]) @ dft_matrix(N)[xi(L, N, c), :]
+    out = []
+    for n in range(len(ncp)):
+        wn = yh[sigma[n]:sigma[n] + 3 * N // 2]
+        th_n = np.conj(unit_phase(c * sigma[n], N))
+        g = []
+        for r in (0, 1):
+            phi_r = np.conj(unit_phase(r * c * ov.L_S, L))
+            g.append(phi_r * th_n * (Gf @ wn[r * N // 2:r * N // 2 + N]) / np.sqrt(ov.I))
+        out.append(g)
+    return np.array(out)
+
+
+def omega(L, phi):
+    """Omega_phi = diag(W_L^(phi k)), k = 0..L-1, W_L = exp(-j 2 pi / L) (Sec. V-A)."""
+    return np.exp(-2j * np.pi * ((phi * np.arange(L)) % L) / L)
+
+
+def rx_sync_subcarriers_reduced(yh, L, N, c, D, ncp):
+    """Sec. V-A simplified joint processing of the FC short IFFTs and the OFDM
+    FFT: per symbol x = Omega_{-L/4} [F (g0 - Omega_{L/2} g1) + Omega_{L/2} g1]
+    with F = Omega_{L/4} C Omega_{-L/4} and the half-band matrix
+    C = W_L S_hat W_L^{-1}, S_hat the synthesis window shifted by L/4, read as
+    diag([1_{L/2}; 0_{L/2}]); times the demodulation's 1/sqrt(L). One short
+    IFFT and one FFT per symbol. Returns (B, L) like rx_sync_subcarriers."""
+    g = rx_sync_blocks_freq(yh, L, N, c, D, ncp)
+    S_hat = np.diag(np.r_[np.ones(L // 2), np.zeros(L // 2)])
+    C = dft_matrix(L) @ S_hat @ idft_matrix(L)
+    F = omega(L, L // 4)[:, None] * C * omega(L, -L // 4)[None, :]
+    out = []
+    for g0, g1 in g:
+        h1 = omega(L, L // 2) * g1
+        out.append(omega(L, -L // 4) * (F @ (g0 - h1) + h1) / np.sqrt(L))
+    return np.stack(out)
+
+
 # ----------------------------------------------------------------- stream --
 def place(parts, length=None):
     """Sum local outputs onto one stream: parts = [(offset, array), ...]."""

@@ -277,6 +277,45 @@ def concat_sync_vs_keepcp(fc, L=16, N=64, c=4, ncp=(9, 5, 6), seed=11):
     return rel(a, np.stack(parts))
 
 
+# ------------------------------------------- RX with OFDM demodulation ----
+def tone_rx_subcarriers(fc, L=32, N=128, c=5, seed=6):
+    """A tone at long bin c + kappa, demodulated per symbol (Sec. IV): one
+    nonzero subcarrier, kappa mod L, of value sqrt(L I) D[kappa + L/2] times
+    the tone's phase at the symbol's first useful high-rate sample."""
+    rng = np.random.default_rng(seed)
+    I = N // L
+    ov = nu.Overlap(L, N)
+    D = rng.uniform(0.1, 1.0, L)
+    ncp = [9, 7, 7, 9]
+    Q = nu.sync_output_len(ncp, ov)
+    t = np.arange(Q)
+    sig = nu.sync_sigma(ncp, N)
+    worst = 0.0
+    for kap in (-L // 2, -3, 0, 5, L // 2 - 1):
+        yh = np.exp(2j * np.pi * (c + kap) * t / N)
+        X = fc.rx_sync_subcarriers(yh, L, N, c, D, ncp)
+        for n, s in enumerate(sig):
+            ref = np.zeros(L, dtype=complex)
+            ref[kap % L] = np.sqrt(L * I) * D[kap + L // 2] * np.exp(2j * np.pi * kap * (s + ov.N_L) / N)
+            worst = max(worst, rel(X[n], ref))
+    return worst
+
+
+def reduced_vs_direct(fc, seed=7):
+    """Sec. V-A: the simplified processing (one IFFT and one FFT per symbol)
+    equals the direct one (two IFFTs, concatenation, FFT) on arbitrary input."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for L, N, c, ncp in ((16, 64, 7, [9, 5, 6]), (32, 128, -11, [20, 18, 18]), (64, 256, 40, [36, 20, 20])):
+        ov = nu.Overlap(L, N)
+        Q = nu.sync_output_len(ncp, ov)
+        yh = _cvec(rng, Q)
+        D = rng.uniform(-1.0, 1.0, L)
+        worst = max(worst, rel(fc.rx_sync_subcarriers_reduced(yh, L, N, c, D, ncp),
+                               fc.rx_sync_subcarriers(yh, L, N, c, D, ncp)))
+    return worst
+
+
 ALL_PINS = {
     "pr1_sync": lambda fc: pr1_sync(fc),
     "pr1_cont_ols": lambda fc: pr1_cont(fc, False),
@@ -299,5 +338,7 @@ ALL_PINS = {
     "adjoint_quarter_ols": lambda fc: adjoint_cont(fc, False, L=32, N=128, c=-9, lam=Fraction(1, 4)),
     "adjoint_sync": lambda fc: adjoint_sync(fc),
     "concat_vs_keepcp": lambda fc: concat_sync_vs_keepcp(fc),
+    "tone_rx_subcarriers": lambda fc: tone_rx_subcarriers(fc),
+    "reduced_vs_direct": lambda fc: reduced_vs_direct(fc),
 }
 TOL = 1e-10

@@ -40,6 +40,18 @@ MUTATIONS = {
     "concat_wrong_half": ("P[rows, L // 4 + np.arange(L // 2)] = 1.0", "P[rows, np.arange(L // 2)] = 1.0"),
     "keep_cp_off_by_one": ("out.append(np.r_[z[0][S_L:3 * L // 4], z[1][L // 4:3 * L // 4]])",
                            "out.append(np.r_[z[0][S_L + 1:3 * L // 4 + 1], z[1][L // 4:3 * L // 4]])"),
+    "demod_no_scale": ("return rx_sync(yh, L, N, c, D, ncp) @ dft_matrix(L) / np.sqrt(L)",
+                       "return rx_sync(yh, L, N, c, D, ncp) @ dft_matrix(L)"),
+    "demod_inverse": ("return rx_sync(yh, L, N, c, D, ncp) @ dft_matrix(L) / np.sqrt(L)",
+                      "return rx_sync(yh, L, N, c, D, ncp) @ idft_matrix(L) * np.sqrt(L)"),
+    "reduced_window_second_half": ("S_hat = np.diag(np.r_[np.ones(L // 2), np.zeros(L // 2)])",
+                                   "S_hat = np.diag(np.r_[np.zeros(L // 2), np.ones(L // 2)])"),
+    "reduced_omega_sign": ("return np.exp(-2j * np.pi * ((phi * np.arange(L)) % L) / L)",
+                           "return np.exp(2j * np.pi * ((phi * np.arange(L)) % L) / L)"),
+    "reduced_block_swap": ("for g0, g1 in g:", "for g1, g0 in g:"),
+    "blocks_freq_no_phase": ("g.append(phi_r * th_n * (Gf @ wn[r * N // 2:r * N // 2 + N]) / np.sqrt(ov.I))",
+                             "g.append(th_n * (Gf @ wn[r * N // 2:r * N // 2 + N]) / np.sqrt(ov.I))"),
+    "blocks_freq_theta_sign": ("th_n = np.conj(unit_phase(c * sigma[n], N))", "th_n = unit_phase(c * sigma[n], N)"),
 }
 
 

@@ -67,7 +67,8 @@ enum {
 enum {
   FC_OP_TX = 0,      /* fc_tx_synthesize: low-rate CP-OFDM in, high-rate out            */
   FC_OP_RX = 1,      /* fc_rx_analyze:    high-rate in, low-rate out                    */
-  FC_OP_ADJ = 2      /* fc_tx_adjoint:    high-rate in, low-rate CP-OFDM-shaped out     */
+  FC_OP_ADJ = 2,     /* fc_tx_adjoint:    high-rate in, low-rate CP-OFDM-shaped out     */
+  FC_OP_RXD = 3      /* fc_rx_demodulate: high-rate in, subcarriers out (synchronised)   */
 };
 
 /*
@@ -137,7 +138,8 @@ fc_status fc_plan_counts(const fc_plan* plan, int32_t* n_sb, int32_t* n_streams)
  *                               [highrate_off[s], highrate_off[s+1])
  * Low-rate layout: FC_OP_TX / FC_OP_ADJ and continuous FC_OP_RX use the
  * concatenated CP-OFDM symbols (sum_n n_short + L_CP,n); synchronised FC_OP_RX
- * returns n_symbols * n_short samples (CP removed, Sec. IV concatenation).
+ * returns n_symbols * n_short samples (CP removed, Sec. IV concatenation), and
+ * FC_OP_RXD n_symbols * n_short subcarrier values.
  * Either pointer may be NULL.
  */
 fc_status fc_plan_layout(const fc_plan* plan, int32_t op, int64_t* lowrate_off,
@@ -191,6 +193,23 @@ fc_status fc_tx_synthesize(fc_plan* plan, const void* lowrate_in, void* highrate
 fc_status fc_rx_analyze(fc_plan* plan, const void* highrate_in, void* lowrate_out, void* stream);
 
 /*
+ * Synchronised FC analysis followed by OFDM demodulation (Sec. IV, with
+ * L_OFDM = n_short): for every symbol n of every subband,
+ * x_hat_n = (1/sqrt(L)) W_L x_hat_OFDM,n, the subcarrier values, computed in
+ * the simplified joint form of Sec. V-A (one short IFFT and one FFT per symbol
+ * instead of two IFFTs and an FFT): with g0, g1 the two blocks' weighted and
+ * phase-rotated bins, x = C(A - B) + B, A[k] = g0[k] j^k, B[k] = g1[k] (-j)^k,
+ * C the half-band matrix W_L diag(1_{L/2}, 0_{L/2}) W_L^{-1}.
+ *   highrate_in      device, high-rate layout, the plan's I/O type.
+ *   subcarriers_out  device, FC_OP_RXD layout (per subband n_symbols * n_short
+ *                    values, symbol by symbol; subcarrier kappa of a symbol at
+ *                    index kappa mod n_short), the plan's I/O type.
+ * Every subband must be synchronised (FC_SYNC_OLA or FC_SYNC_OLS), else
+ * FC_E_STATE. Asynchronous on `stream`; errors as fc_rx_analyze.
+ */
+fc_status fc_rx_demodulate(fc_plan* plan, const void* highrate_in, void* subcarriers_out, void* stream);
+
+/*
  * Exact adjoint of fc_tx_synthesize (used for gradients): highrate_in ->
  * lowrate_out in the FC_OP_TX low-rate layout, so that
  * <tx(x), y> = <x, adjoint(y)> for the plan's current weights.
@@ -226,7 +245,7 @@ fc_status fc_plan_stats(const fc_plan* plan, int32_t op, int64_t* n_blocks, int6
                         int64_t* n_launches);
 
 /*
- * Tuning of operation op (FC_OP_TX, FC_OP_RX, FC_OP_ADJ; FC_OP_ADJ also sets
+ * Tuning of operation op (FC_OP_TX, FC_OP_RX, FC_OP_ADJ, FC_OP_RXD; FC_OP_ADJ also sets
  * the weight gradient's work split):
  *   run_len  FC blocks per workgroup task (consecutive blocks of one group;
  *            0 = the planner's choice from the total block count; TX runs of

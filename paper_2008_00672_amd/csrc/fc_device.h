@@ -799,6 +799,183 @@ __global__ __launch_bounds__(kThreads, 4) void fc_rx_kernel(LaunchArgs a, int) {
   }
 }
 
+// ------------------------------------------------ demodulating RX -------
+// v * j^k for k = 0..3.
+__device__ __forceinline__ float2 rot_j(float2 v, int k) {
+  const float2 r = (k & 1) ? make_float2(-v.y, v.x) : v;
+  return (k & 2) ? make_float2(-r.x, -r.y) : r;
+}
+
+// First pass of the per-symbol IFFT: V[u] = A[u] - B[u], A from the first
+// block (stored), B[u] = g1[u] (-j)^u from the second block's region.
+template <int NT, int L> struct LoadV {
+  const float2* A; const float2* R; const float* D; float2 ph;
+  float d[16];
+  __device__ __forceinline__ void prefetch(int tid) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      int u, b;
+      if (first_pos<NT, L, 0>(s, tid, u, b)) d[s] = D[(u + (L >> 1)) & (L - 1)];
+    }
+  }
+  __device__ __forceinline__ float2 operator()(int slot, int u, int, int up) const {
+    const float2 g1 = cscale(cmul(R[up], ph), d[slot]);
+    return csub(A[up], rot_j(g1, (-u) & 3));
+  }
+};
+
+// Last pass of that IFFT: the half-band window keeps the first L/2 samples
+// (and applies the inverse transform's 1/L).
+struct StoreMask : NoPrefetch {
+  float2* A; int half; float inv_l;
+  __device__ __forceinline__ void operator()(int, int t, float2 v, int tp) const {
+    A[tp] = t < half ? make_float2(v.x * inv_l, v.y * inv_l) : make_float2(0.f, 0.f);
+  }
+};
+
+// First pass of the FFT back: the windowed samples in place.
+struct LoadPadded : NoPrefetch {
+  const float2* A;
+  __device__ __forceinline__ float2 operator()(int, int, int, int ip) const { return A[ip]; }
+};
+
+// Last pass of that FFT: x[u] = (C V)[u] + B[u], scaled by 1/sqrt(L), to the
+// symbol's subcarrier u.
+template <int IO, int NT, int L> struct StoreSubcarriers {
+  const float2* R; const float* D; float2 ph; typename Io<IO>::T* out; float scale;
+  float d[16];
+  __device__ __forceinline__ void prefetch(int tid) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int u = last_pos<NT, L, 0>(s, tid);
+      if (u >= 0) d[s] = D[(u + (L >> 1)) & (L - 1)];
+    }
+  }
+  __device__ __forceinline__ void operator()(int slot, int u, float2 v, int up) const {
+    const float2 b = rot_j(cscale(cmul(R[up], ph), d[slot]), (-u) & 3);
+    const float2 x = cadd(v, b);
+    Io<IO>::st(out, u, make_float2(x.x * scale, x.y * scale));
+  }
+};
+
+// Synchronised RX with OFDM demodulation in the simplified joint form of
+// Sec. V-A. Tasks hold whole symbols (block pairs). Per symbol: the first
+// block's long FFT is scattered into the subband regions and every subband
+// stores A[u] = g0[u] j^u in its second region (the same layout, above the
+// spectrum); the second block's long FFT is scattered likewise, then each
+// subband runs V = A - B -> IFFT -> keep the first half -> FFT -> + B in its
+// second region and writes the L subcarriers. Subbands with L <= 1024 run on
+// one wave (assignment as the RX kernel), longer ones on the workgroup.
+template <int IO, int NL>
+__global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
+  extern __shared__ float2 smem[];
+  const int n = gridDim.x;
+  int task = blockIdx.x;
+  if ((n & 7) == 0) task = (blockIdx.x & 7) * (n >> 3) + (blockIdx.x >> 3);
+  if (task >= a.n_task) return;
+  const TaskDesc T = a.task[task];
+  const GroupDesc G = a.grp[T.group];
+  float2* S = smem;                                        // spectrum, then the block's regions
+  float2* Ab = smem + G.scr_off;                           // second regions (A, then V in place)
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = ((tid >> 6) + blockIdx.x) & 3;
+  const float2* tw = reinterpret_cast<const float2*>(a.twpass);
+  const uint64_t* map = a.rxmap + G.map_off;
+  LoadAhead<IO, kThreads, NL> lh;
+  {
+    const BlockDesc B0 = a.blk[T.blk_first];
+    lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
+  }
+  for (int bi = 0; bi + 1 < T.blk_count; bi += 2) {
+    const BlockDesc B0 = a.blk[T.blk_first + bi];
+    const BlockDesc B1 = a.blk[T.blk_first + bi + 1];
+    StoreScatter sc;
+    sc.S = S; sc.map = map;
+    // ---- first block: spectrum -> regions -> A
+    __syncthreads();
+    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sc, tw);
+    lh.issue(at<IO>(a.in, B1.t0), B1.hlo, B1.hhi, tid);
+    __syncthreads();
+    for (int m = 0; m < G.n_sb; ++m) {
+      const SbDesc Sb = a.sb[G.sb_first + m];
+      const bool mine = Sb.wave >= 0 ? Sb.wave == wave : true;
+      if (!mine) continue;
+      const int step = Sb.wave >= 0 ? 64 : kThreads;
+      const float2 ph = make_float2(a.bsb[B0.bs + m].ph.x, a.bsb[B0.bs + m].ph.y);
+      const float* D = a.weights + Sb.w_off;
+      const float2* R = S + Sb.cofs;
+      float2* A = Ab + Sb.cofs;
+      for (int u = Sb.wave >= 0 ? lane : tid; u < Sb.L; u += step) {
+        const int up = pad(u);
+        A[up] = rot_j(cscale(cmul(R[up], ph), D[(u + (Sb.L >> 1)) & (Sb.L - 1)]), u & 3);
+      }
+    }
+    __syncthreads();
+    // ---- second block: spectrum -> regions; per subband the joint transform
+    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sc, tw);
+    if (bi + 2 < T.blk_count) {
+      const BlockDesc Bn = a.blk[T.blk_first + bi + 2];
+      lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
+    }
+    __syncthreads();
+    auto run_wave = [&](auto lc) {
+      constexpr int LL = decltype(lc)::value;
+      if constexpr (LL <= NL) {
+        for (int m = 0; m < G.n_sb; ++m) {
+          const SbDesc Sb = a.sb[G.sb_first + m];
+          if (Sb.L != LL || Sb.wave != wave) continue;
+          const BlockSb Z = a.bsb[B1.bs + m];
+          const float2 ph = make_float2(Z.ph.x, Z.ph.y);
+          float2* A = Ab + Sb.cofs;
+          LoadV<64, LL> lv;
+          lv.A = A; lv.R = S + Sb.cofs; lv.D = a.weights + Sb.w_off; lv.ph = ph;
+          StoreMask sm;
+          sm.A = A; sm.half = LL / 2; sm.inv_l = 1.f / LL;
+          fft_run<64, LL, 0, +1>(A, lane, lv, sm, tw);
+          wave_sync();
+          LoadPadded lp;
+          lp.A = A;
+          StoreSubcarriers<IO, 64, LL> so;
+          so.R = S + Sb.cofs; so.D = a.weights + Sb.w_off; so.ph = ph; so.out = at<IO>(a.out, Z.x0);
+          so.scale = rsqrtf((float)LL);
+          fft_run<64, LL, 0, -1>(A, lane, lp, so, tw);
+        }
+      }
+    };
+    run_wave(SizeC<1024>()); run_wave(SizeC<512>()); run_wave(SizeC<256>()); run_wave(SizeC<128>());
+    run_wave(SizeC<64>()); run_wave(SizeC<32>()); run_wave(SizeC<16>());
+    auto run_group = [&](auto lc) {
+      constexpr int LL = decltype(lc)::value;
+      if constexpr (LL <= NL) {
+        for (int m = 0; m < G.n_sb; ++m) {
+          const SbDesc Sb = a.sb[G.sb_first + m];
+          if (Sb.L != LL || Sb.wave >= 0) continue;
+          const BlockSb Z = a.bsb[B1.bs + m];
+          const float2 ph = make_float2(Z.ph.x, Z.ph.y);
+          float2* A = Ab + Sb.cofs;
+          LoadV<kThreads, LL> lv;
+          lv.A = A; lv.R = S + Sb.cofs; lv.D = a.weights + Sb.w_off; lv.ph = ph;
+          StoreMask sm;
+          sm.A = A; sm.half = LL / 2; sm.inv_l = 1.f / LL;
+          __syncthreads();
+          fft_run<kThreads, LL, 0, +1>(A, tid, lv, sm, tw);
+          __syncthreads();
+          LoadPadded lp;
+          lp.A = A;
+          StoreSubcarriers<IO, kThreads, LL> so;
+          so.R = S + Sb.cofs; so.D = a.weights + Sb.w_off; so.ph = ph; so.out = at<IO>(a.out, Z.x0);
+          so.scale = rsqrtf((float)LL);
+          fft_run<kThreads, LL, 0, -1>(A, tid, lp, so, tw);
+        }
+      }
+    };
+    if (G.n_long_sb > 0) {
+      run_group(SizeC<2048>());
+      run_group(SizeC<4096>());
+    }
+  }
+}
+
 // ---------------------------------------------------- weight gradient ---
 // Last pass of the short FFT of the forward input block: bin u (natural
 // order, weight index p = (u + L/2) mod L) adds Re(conj(A) X) to its LDS
@@ -914,7 +1091,7 @@ __global__ __launch_bounds__(kThreads) void fc_zero_kernel(void* out, int64_t n)
 // ------------------------------------------------------ per-I/O dispatch ---
 // Kernel classes: 0 = TX pruned (size = L, aux = log2 I), 1 = TX full
 // (size = N, aux = largest L), 2 = RX and adjoint (size = N), 3 = weight
-// gradient (size = N).
+// gradient (size = N), 4 = demodulating RX (size = N).
 template <int IO, int L>
 hipError_t launch_pruned(const LaunchArgs& a, int logi, size_t lds, hipStream_t s, dim3 grid) {
   dim3 block(kThreads);
@@ -936,6 +1113,8 @@ hipError_t launch_size(int cls, const LaunchArgs& a, int aux, size_t lds, hipStr
     hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ>), grid, block, lds, s, a, aux);
   } else if (cls == 3) {
     hipLaunchKernelGGL((fc_wgrad_kernel<IO, SZ>), grid, block, lds, s, a, aux);
+  } else if (cls == 4) {
+    hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ>), grid, block, lds, s, a, aux);
   } else {
     hipLaunchKernelGGL((fc_rx_kernel<IO, SZ>), grid, block, lds, s, a, aux);
   }
@@ -988,6 +1167,9 @@ hipError_t lds_limits_io(size_t bytes) {
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
     hipError_t r4 = hipFuncSetAttribute((const void*)fc_wgrad_kernel<IO, SZ>,                       \
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
+    hipError_t r5 = hipFuncSetAttribute((const void*)fc_rxd_kernel<IO, SZ>,                         \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
+    if (r5 != hipSuccess) e = r5;                                                                   \
     if (r1 != hipSuccess) e = r1;                                                                   \
     if (r2 != hipSuccess) e = r2;                                                                   \
     if (r3 != hipSuccess) e = r3;                                                                   \

@@ -114,9 +114,9 @@ struct fc_plan {
   float* d_w = nullptr;
   Cf* d_tw = nullptr;
   Cf* d_twp = nullptr;           // per-pass twiddle bases
-  Op op[3];
-  int run_len[3] = {0, 0, 0};    // blocks per task per op (0: planner heuristic)
-  int conc[3] = {kMaxConc, kMaxConc, kMaxConc};   // per op: launches of one independent set in flight
+  Op op[4];
+  int run_len[4] = {0, 0, 0, 0}; // blocks per task per op (0: planner heuristic)
+  int conc[4] = {kMaxConc, kMaxConc, kMaxConc, kMaxConc};   // per op: launches of one independent set in flight
   hipStream_t side[kMaxConc - 1] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kMaxConc - 1] = {};
@@ -222,7 +222,8 @@ fc_status upload(const std::vector<T>& h, T** d) {
 }
 
 // Block windows of one subband for one operation.
-// kind: 0 TX, 1 RX (paper's receiver of the mode), 2 adjoint of TX.
+// kind: 0 TX, 1 RX (paper's receiver of the mode), 2 adjoint of TX,
+// 3 synchronised RX with OFDM demodulation (Sec. V-A simplified form).
 struct Win { int64_t x0; int lo, hi; };
 
 Win clip_valid(const Sub& s, int64_t xrel, int lo, int hi, int64_t len) {
@@ -236,16 +237,18 @@ void build_op(fc_plan* P, int kind) {
   Op& op = P->op[kind];
   op = Op();
   const int nsb = (int)P->subs.size();
-  // validity: TX needs CONT_* or SYNC_OLA; ADJ likewise; RX any
+  // validity: TX needs CONT_* or SYNC_OLA; ADJ likewise; RX any; the
+  // demodulating RX needs synchronised subbands
   for (const Sub& s : P->subs) {
-    if (kind != 1 && s.d.mode == FC_SYNC_OLS) return;
+    if ((kind == 0 || kind == 2) && s.d.mode == FC_SYNC_OLS) return;
+    if (kind == 3 && !s.sync) return;
   }
   op.valid = true;
   // low-rate layout
   op.lo_off.assign(nsb + 1, 0);
   for (int m = 0; m < nsb; ++m) {
     const Sub& s = P->subs[m];
-    const int64_t len = (kind == 1 && s.sync) ? (int64_t)s.d.n_symbols * s.L : s.n_in;
+    const int64_t len = ((kind == 1 || kind == 3) && s.sync) ? (int64_t)s.d.n_symbols * s.L : s.n_in;
     op.lo_off[m + 1] = op.lo_off[m] + len;
   }
   // processing groups of this operation: the plan's groups, except that an RX
@@ -402,6 +405,9 @@ void build_op(fc_plan* P, int kind) {
             // Sec. IV concatenation: keep [L/4, 3L/4) of both blocks, CP removed
             const int64_t xrel = (int64_t)n * L + (int64_t)r * (L / 2) - L / 4;
             w = Win{xrel, L / 4, 3 * L / 4};
+          } else if (kind == 3) {
+            // the symbol's L subcarriers, written when its second block is done
+            w = Win{(int64_t)n * L, 0, L};
           } else {
             const int64_t xrel = s.pos[n] + (int64_t)r * (L / 2) - S_L;
             w = (r == 0) ? Win{xrel, S_L, 3 * L / 4} : Win{xrel, L / 4, 3 * L / 4};
@@ -419,6 +425,7 @@ void build_op(fc_plan* P, int kind) {
         z.x0 = op.lo_off[m] + w.x0;
         z.lo = w.lo; z.hi = w.hi;
         if (kind == 0) z.ph = unit_phase(phase_num, N, std::sqrt((double)s.I) / N);
+        else if (kind == 3) z.ph = unit_phase(-phase_num, N, 1.0 / std::sqrt((double)s.I));   // g^(r) itself
         else z.ph = unit_phase(-phase_num, N, 1.0 / (std::sqrt((double)s.I) * L));
         op.bsb.push_back(z);
       }
@@ -480,17 +487,20 @@ void build_op(fc_plan* P, int kind) {
       any_ola_rx |= acc;
       int64_t total_blocks = 0;
       for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
-      const int K = acc ? 1
-                        : P->run_len[kind] > 0 ? P->run_len[kind]
-                                               : (int)std::max<int64_t>(2, std::min<int64_t>(8, total_blocks / 4096));
+      int K = acc ? 1
+                  : P->run_len[kind] > 0 ? P->run_len[kind]
+                                         : (int)std::max<int64_t>(2, std::min<int64_t>(8, total_blocks / 4096));
+      if (kind == 3) K += K & 1;                        // whole symbols per task
       for (int b = 0; b < nblk; b += K) {
         TaskDesc t{};
         t.group = (int)g; t.blk_first = first_blk + b; t.blk_count = std::min(K, nblk - b);
         t.accumulate = acc ? 1 : 0;
         PhaseTasks& ph = acc ? ((b & 1) ? rx_odd : rx_even) : rx_all;
-        ClassTasks& ct = ph.cls[std::make_tuple(2, N, 0)];
+        ClassTasks& ct = ph.cls[std::make_tuple(kind == 3 ? 4 : 2, N, 0)];
         ct.t.push_back(t);
-        ct.lds = std::max(ct.lds, (size_t)std::max(lds_elems(N), lsum) * 8);
+        // demodulating RX: a second set of subband regions holds the first
+        // block's spectra while the second block's long FFT runs
+        ct.lds = std::max(ct.lds, (size_t)(std::max(lds_elems(N), lsum) + (kind == 3 ? lsum : 0)) * 8);
         const GroupDesc& gd = op.grp[g];
         ct.glds = std::max(ct.glds, (size_t)(gd.acc_off + (gd.acc_len + 1) / 2) * 8);
       }
@@ -755,7 +765,7 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   P->w_off.resize(n_sb);
   for (int m = 0; m < n_sb; ++m) { P->w_off[m] = P->w_total; P->w_total += P->subs[m].L; }
   // host tables
-  for (int k = 0; k < 3; ++k) build_op(P, k);
+  for (int k = 0; k < 4; ++k) build_op(P, k);
   if (device < 0) {        // host-only plan: schedules and layouts, no device state
     *plan = P;
     return FC_OK;
@@ -791,9 +801,9 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   if (!st) st = upload(tw, &P->d_tw);
   if (!st) st = upload(twp, &P->d_twp);
   if (!st) st = upload(w, &P->d_w);
-  for (int k = 0; k < 3 && !st; ++k) st = upload_op(P->op[k]);
+  for (int k = 0; k < 4 && !st; ++k) st = upload_op(P->op[k]);
   size_t lds_max = 0;
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < 4; ++k)
     for (auto& ph : P->op[k].phases) lds_max = std::max(lds_max, std::max(ph.lds, ph.glds));
   if (!st && lds_max > 65536 && set_lds_limits(lds_max) != hipSuccess) st = FC_E_UNSUPPORTED;
   // side streams (default priority) and fork/join events
@@ -819,7 +829,7 @@ void fc_plan_destroy(fc_plan* P) {
     if (P->ev_join[q]) (void)hipEventDestroy(P->ev_join[q]);
   }
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
-  for (int k = 0; k < 3; ++k) free_op(P->op[k]);
+  for (int k = 0; k < 4; ++k) free_op(P->op[k]);
   (void)hipFree(P->d_w);
   (void)hipFree(P->d_tw);
   (void)hipFree(P->d_twp);
@@ -835,7 +845,7 @@ fc_status fc_plan_counts(const fc_plan* P, int32_t* n_sb, int32_t* n_streams) {
 }
 
 fc_status fc_plan_layout(const fc_plan* P, int32_t op, int64_t* lowrate_off, int64_t* highrate_off) {
-  if (!P || op < FC_OP_TX || op > FC_OP_ADJ) return FC_E_ARG;
+  if (!P || op < FC_OP_TX || op > FC_OP_RXD) return FC_E_ARG;
   const Op& o = P->op[op];
   if (!o.valid) return FC_E_STATE;
   if (lowrate_off) std::copy(o.lo_off.begin(), o.lo_off.end(), lowrate_off);
@@ -903,7 +913,7 @@ fc_status fc_get_weights(const fc_plan* P, int32_t sb, float* w_host, int32_t n)
 }
 
 fc_status fc_plan_set_tuning(fc_plan* P, int32_t op, int32_t run_len, int32_t conc) {
-  if (!P || op < 0 || op > 2 || run_len < 0 || run_len > 256 || conc < 1 || conc > kMaxConc) return FC_E_ARG;
+  if (!P || op < 0 || op > 3 || run_len < 0 || run_len > 256 || conc < 1 || conc > kMaxConc) return FC_E_ARG;
   if (!P->op[op].valid) return FC_E_STATE;
   if (P->device >= 0) {
     int cur = -1;
@@ -921,7 +931,7 @@ fc_status fc_plan_set_tuning(fc_plan* P, int32_t op, int32_t run_len, int32_t co
 }
 
 fc_status fc_plan_get_tuning(const fc_plan* P, int32_t op, int32_t* run_len, int32_t* conc) {
-  if (!P || op < 0 || op > 2) return FC_E_ARG;
+  if (!P || op < 0 || op > 3) return FC_E_ARG;
   if (run_len) *run_len = P->run_len[op];
   if (conc) *conc = P->conc[op];
   return FC_OK;
@@ -929,13 +939,14 @@ fc_status fc_plan_get_tuning(const fc_plan* P, int32_t op, int32_t* run_len, int
 
 fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, void* stream, int32_t* best_run_len,
                            int32_t* best_conc, float* best_ms) {
-  if (!P || op < 0 || op > 2 || !in || !out) return FC_E_ARG;
+  if (!P || op < 0 || op > 3 || !in || !out) return FC_E_ARG;
   if (!P->op[op].valid || P->device < 0) return FC_E_STATE;
   const hipStream_t st = (hipStream_t)stream;
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
-  const std::vector<int> lens = op == FC_OP_TX ? std::vector<int>{0, 8, 16, 32, 64}
-                                               : std::vector<int>{0, 1, 2, 4, 8, 16};
+  const std::vector<int> lens = op == FC_OP_TX    ? std::vector<int>{0, 8, 16, 32, 64}
+                               : op == FC_OP_RXD ? std::vector<int>{0, 2, 4, 8, 16}
+                                                 : std::vector<int>{0, 1, 2, 4, 8, 16};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   fc_status result = FC_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) result = FC_E_DEVICE;
@@ -974,7 +985,7 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
 }
 
 fc_status fc_plan_stats(const fc_plan* P, int32_t op, int64_t* n_blocks, int64_t* n_tasks, int64_t* n_launches) {
-  if (!P || op < FC_OP_TX || op > FC_OP_ADJ) return FC_E_ARG;
+  if (!P || op < FC_OP_TX || op > FC_OP_RXD) return FC_E_ARG;
   const Op& o = P->op[op];
   if (!o.valid) return FC_E_STATE;
   if (n_blocks) *n_blocks = (int64_t)o.blk.size();
@@ -991,6 +1002,11 @@ fc_status fc_tx_synthesize(fc_plan* P, const void* in, void* out, void* stream) 
 fc_status fc_rx_analyze(fc_plan* P, const void* in, void* out, void* stream) {
   if (!P) return FC_E_ARG;
   return run_op(P, FC_OP_RX, in, out, (hipStream_t)stream);
+}
+
+fc_status fc_rx_demodulate(fc_plan* P, const void* in, void* out, void* stream) {
+  if (!P) return FC_E_ARG;
+  return run_op(P, FC_OP_RXD, in, out, (hipStream_t)stream);
 }
 
 fc_status fc_tx_adjoint(fc_plan* P, const void* in, void* out, void* stream) {

@@ -17,7 +17,7 @@ CONT_OLA, CONT_OLS, SYNC_OLA, SYNC_OLS = 0, 1, 2, 3
 MODES = {"cont_ola": CONT_OLA, "cont_ols": CONT_OLS, "sync_ola": SYNC_OLA, "sync_ols": SYNC_OLS}
 IO_C64, IO_F16, IO_BF16 = 0, 1, 2
 IOS = {"c64": IO_C64, "f16": IO_F16, "bf16": IO_BF16}
-OP_TX, OP_RX, OP_ADJ = 0, 1, 2
+OP_TX, OP_RX, OP_ADJ, OP_RXD = 0, 1, 2, 3
 
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -46,6 +46,7 @@ EXPORTS = {
     "fc_tx_synthesize": (_I32, [_P, _P, _P, _P]),
     "fc_rx_analyze": (_I32, [_P, _P, _P, _P]),
     "fc_tx_adjoint": (_I32, [_P, _P, _P, _P]),
+    "fc_rx_demodulate": (_I32, [_P, _P, _P, _P]),
     "fc_tx_weight_grad": (_I32, [_P, _P, _P, _P, _P]),
     "fc_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
     "fc_plan_get_tuning": (_I32, [_P, _I32, _I32P, _I32P]),
@@ -231,6 +232,16 @@ class Plan:
             out = self.empty(int(lo[-1]))
         self._check_buf(out, int(lo[-1]), "low-rate output")
         _check(lib().fc_rx_analyze(self._h, _ptr(y), _ptr(out), _stream_handle(stream)), "fc_rx_analyze")
+        return out
+
+    def rx_demod(self, y, out=None, stream=None):
+        """Synchronised RX + OFDM demodulation: subcarrier values per symbol."""
+        lo, hi = self.layout(OP_RXD)
+        self._check_buf(y, int(hi[-1]), "high-rate input")
+        if out is None:
+            out = self.empty(int(lo[-1]))
+        self._check_buf(out, int(lo[-1]), "subcarrier output")
+        _check(lib().fc_rx_demodulate(self._h, _ptr(y), _ptr(out), _stream_handle(stream)), "fc_rx_demodulate")
         return out
 
     def adjoint(self, y, out=None, stream=None):

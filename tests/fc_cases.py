@@ -90,6 +90,18 @@ def oracle_rx(subbands, streams, Ds):
     return outs
 
 
+def oracle_rxd(subbands, streams, Ds):
+    """Per subband (B, L) subcarrier values of the synchronised RX followed by
+    OFDM demodulation (the direct definition), flattened symbol by symbol."""
+    off, lens, P = stream_offsets(subbands)
+    outs = []
+    for i, s in enumerate(subbands):
+        p = P[i]
+        seg = streams[s["stream"]][off[i]:off[i] + p["Q"]]
+        outs.append(ofc.rx_sync_subcarriers(seg, p["L"], p["N"], p["c"], Ds[i], p["ncp"]).ravel())
+    return outs
+
+
 def oracle_adj(subbands, streams, Ds):
     off, lens, P = stream_offsets(subbands)
     outs = []

@@ -183,6 +183,31 @@ def test_tuning_host_plan():
             p.set_tuning(fc.OP_TX, **dict(dict(run_len=0, conc=4), **bad))
 
 
+def test_rx_demod_layout_and_validity():
+    """The demodulating RX has the synchronised RX layout (L values per symbol)
+    and needs synchronised subbands."""
+    fc = _lib()
+    sbs, _ = W.mixed_numerology("sync_ols")
+    p = _plan(sbs)
+    assert list(p.layout(fc.OP_RXD)[0]) == list(p.layout(fc.OP_RX)[0])
+    st = p.stats(fc.OP_RXD)
+    assert st["blocks"] == p.stats(fc.OP_RX)["blocks"]
+    s = W.subband(15, 2, 96, 8, 128, 1024, 0, "cont_ols")
+    with pytest.raises(fc.FcError):
+        _plan([s]).layout(fc.OP_RXD)
+
+
+def test_rx_demod_tasks_hold_whole_symbols():
+    fc = _lib()
+    sbs, _ = W.rx_filterbank(n_symbols=10)
+    p = _plan(sbs)
+    for run_len in (1, 3, 5):
+        p.set_tuning(fc.OP_RXD, run_len, 1)
+        # 20 blocks in runs of run_len rounded up to even
+        k = run_len + (run_len & 1)
+        assert p.stats(fc.OP_RXD)["tasks"] == -(-20 // k)
+
+
 def test_tuning_rejects_missing_op():
     fc = _lib()
     s = W.subband(15, 2, 96, 8, 128, 1024, 0, "sync_ols")

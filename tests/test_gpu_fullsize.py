@@ -5,12 +5,14 @@ piece at a time.
 TX: 256 uneven carriers x 32 slot-batches (8192 streams), FP16 I/Q; sampled
 carriers of sampled batches against the oracle (FP16 gate -60 dB).
 RX: 8 subbands of a 100 MHz carrier x 100 frames, BF16 I/Q; the first 14
-symbols of sampled frames against the oracle (BF16 gate -50 dB).
+symbols of sampled frames against the oracle (BF16 gate -50 dB), for the
+time-domain analysis and for the demodulating receiver.
 """
 import numpy as np
 import pytest
 
-from fc_cases import GATE_DB, from_device, make_inputs, oracle_rx, oracle_tx, rx_frame_input, to_device
+from fc_cases import (GATE_DB, from_device, make_inputs, oracle_rx, oracle_rxd, oracle_tx, rx_frame_input,
+                      stream_offsets, to_device)
 from fcsynth import workloads as W
 from oracle import metrics
 from oracle import weights as ow
@@ -48,27 +50,28 @@ def test_batched_tx_full_size():
             assert e <= GATE_DB["f16"]
 
 
-def test_rx_filterbank_full_size():
+@pytest.mark.parametrize("demod", [False, True], ids=["rx", "rx_demod"])
+def test_rx_filterbank_full_size(demod):
     import torch
-    from paper_2008_00672_amd import OP_RX, Plan
+    from paper_2008_00672_amd import OP_RX, OP_RXD, Plan
     sbs, meta = W.rx_filterbank()
+    op = OP_RXD if demod else OP_RX
     allsb = [dict(s, stream=f) for f in range(RX_FRAMES) for s in sbs]
     p = Plan(allsb, io="bf16", device=0)
     y1 = rx_frame_input(sbs, meta["qam"], meta["seed"], meta["snr_db"])
-    lo, hi = p.layout(OP_RX)
+    lo, hi = p.layout(op)
     assert len(y1) == hi[1] - hi[0]
     r = to_device(y1, "bf16").repeat(RX_FRAMES, 1).contiguous()
     z = p.empty(int(lo[-1]))
-    tune = p.autotune(OP_RX, r, z)
-    print("RX autotune:", tune, flush=True)
-    z = p.rx(r, z)
+    tune = p.autotune(op, r, z)
+    print("autotune:", tune, flush=True)
+    z = p.rx_demod(r, z) if demod else p.rx(r, z)
     torch.cuda.synchronize()
     B = 14
     sub = [dict(s, n_symbols=B) for s in sbs]
-    from fc_cases import stream_offsets
     _, lens, _ = stream_offsets(sub)
     Ds = [ow.rc_weights(s["n_short"], s["n_active"], s["n_tb"]) for s in sbs]
-    refs = oracle_rx(sub, [y1[:lens[0]]], Ds)
+    refs = (oracle_rxd if demod else oracle_rx)(sub, [y1[:lens[0]]], Ds)
     for f in (0, 41, RX_FRAMES - 1):
         for m, ref in enumerate(refs):
             j = f * len(sbs) + m

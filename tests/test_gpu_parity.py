@@ -9,8 +9,8 @@ stages gives about -125 dB); the FP16/BF16 gates are the storage floors
 import numpy as np
 import pytest
 
-from fc_cases import (GATE_DB, from_device, make_inputs, oracle_adj, oracle_rx, oracle_tx, stream_offsets,
-                      to_device)
+from fc_cases import (GATE_DB, from_device, make_inputs, oracle_adj, oracle_rx, oracle_rxd, oracle_tx,
+                      stream_offsets, to_device)
 from fcsynth import workloads as W
 from oracle import metrics
 
@@ -47,22 +47,22 @@ def run_tx(subbands, io, seed=0, qam=16, weights="rc"):
     return got, ref
 
 
-def run_rx(subbands, io, seed=0, weights="rc", adjoint=False):
+def run_rx(subbands, io, seed=0, weights="rc", adjoint=False, demod=False):
     import torch
-    from paper_2008_00672_amd import OP_ADJ, OP_RX
+    from paper_2008_00672_amd import OP_ADJ, OP_RX, OP_RXD
     rng = np.random.default_rng(seed)
     _, lens, _ = stream_offsets(subbands)
     streams = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in lens]
     _, Ds, _ = make_inputs(subbands, 4, seed + 1, weights)
     p = _plan(subbands, io, Ds)
-    op = OP_ADJ if adjoint else OP_RX
+    op = OP_ADJ if adjoint else (OP_RXD if demod else OP_RX)
     lo, hi = p.layout(op)
     assert list(np.diff(hi)) == lens
     dev_in = to_device(_cat(streams), io)
-    z = p.adjoint(dev_in) if adjoint else p.rx(dev_in)
+    z = p.adjoint(dev_in) if adjoint else (p.rx_demod(dev_in) if demod else p.rx(dev_in))
     torch.cuda.synchronize()
     got = _split(from_device(z, io), lo)
-    ref = (oracle_adj if adjoint else oracle_rx)(subbands, streams, Ds)
+    ref = (oracle_adj if adjoint else (oracle_rxd if demod else oracle_rx))(subbands, streams, Ds)
     return got, ref
 
 
@@ -130,6 +130,30 @@ def test_rx_split_groups(name, adjoint):
 def test_rx_tiny(name):
     got, ref = run_rx(TINY_RX[name], "c64", seed=3, weights="random")
     assert_gate(got, ref, "c64", name)
+
+
+DEMOD = {
+    "sync_16_64": [tiny("sync_ols", ncp=CP_FRAC)],
+    "sync_ola_64_256": [tiny("sync_ola", L=64, N=256, c=-40, ncp=[20, 18, 18, 18, 20], K=40, n_tb=8)],
+    "sync_two_sb": TINY_RX["sync_two_sb"],
+    "six_overlapping": [W.subband(15, 2, 24, 4, 64, 256, c, "sync_ols") for c in (-12, -6, 0, 6, 12, 18)],
+    "four_long": [W.subband(15, 2, 1000, 16, 2048, 4096, c, "sync_ols") for c in (-1000, -300, 300, 1000)],
+}
+
+
+@pytest.mark.parametrize("name", sorted(DEMOD))
+def test_rx_demod_tiny(name):
+    """Sec. V-A simplified RX + demodulation against the direct definition."""
+    got, ref = run_rx(DEMOD[name], "c64", seed=13, weights="random", demod=True)
+    assert_gate(got, ref, "c64", name)
+
+
+@pytest.mark.parametrize("io", ["c64", "bf16"])
+def test_rx_demod_filterbank(io):
+    """The 100 MHz 8-subband filter bank, 28 symbols."""
+    sbs, meta = W.rx_filterbank(n_symbols=28)
+    got, ref = run_rx(sbs, io, seed=meta["seed"], demod=True)
+    assert_gate(got, ref, io, "filterbank demod")
 
 
 @pytest.mark.parametrize("name", ["cont_ols_16_64", "cont_ola_16_64", "sync_ola_frac"])

@@ -159,6 +159,20 @@ def rx_cost(sbs, bytes_per_sample):
     return (lo[-1] + hi[-1]) * bytes_per_sample, flops, int(hi[-1])
 
 
+def rxd_cost(sbs):
+    """Flops of the demodulating RX per call: per symbol two long FFTs per
+    stream and per subband one short IFFT and one FFT (5 L log2 L each) plus
+    the bin-wise products of the joint form (A, V, x: 18 L)."""
+    flops = 0.0
+    for st in sorted(set(s["stream"] for s in sbs)):
+        s0 = next(s for s in sbs if s["stream"] == st)
+        flops += 2 * s0["n_symbols"] * 5 * s0["n_long"] * math.log2(s0["n_long"])
+    for s in sbs:
+        L = s["n_short"]
+        flops += s["n_symbols"] * (2 * 5 * L * math.log2(L) + 18 * L)
+    return flops
+
+
 def traffic(op):
     """HBM bytes per call of op from the committed rocprofv3 counter summary
     (profiles/traffic_<op>.json), or None when the kernel sources changed
@@ -267,7 +281,7 @@ def main():
               file=sys.stderr)
         return 2
     import torch
-    from paper_2008_00672_amd import Graph, Plan, OP_RX, OP_TX
+    from paper_2008_00672_amd import Graph, Plan, OP_RX, OP_RXD, OP_TX
 
     if args.copy_calib:
         n = 256 << 20
@@ -311,6 +325,7 @@ def main():
     # TX call and one RX call captured as HIP graphs on a side stream
     gs = torch.cuda.Stream()
     torch.cuda.synchronize()
+    rl = rc = 0
     if args.tuning:
         tl, tc, rl, rc = [int(v) for v in args.tuning.split(",")]
         ptx.set_tuning(OP_TX, tl, tc)
@@ -350,6 +365,34 @@ def main():
     log("step %.3f ms: TX %.3f ms (%.0f GB/s, %.1f TFLOP/s), RX %.3f ms (%.0f GB/s, %.1f TFLOP/s)" % (
         ms, tx_ms, tx_bytes / tx_ms / 1e6, tx_flops / tx_ms / 1e9, rx_ms, rx_bytes / rx_ms / 1e6,
         rx_flops / rx_ms / 1e9))
+
+    # the demodulating receiver (Sec. V-A simplified form) on the same RX
+    # workload, outside the step: subcarriers instead of time-domain symbols
+    zd_dev = prx.empty(int(prx.layout(OP_RXD)[0][-1]))
+    if args.tuning:
+        prx.set_tuning(OP_RXD, rl, rc)
+        tune["rx_demod"] = prx.get_tuning(OP_RXD)
+    else:
+        tune["rx_demod"] = prx.autotune(OP_RXD, r_dev, zd_dev, stream=gs)
+    with Graph(gs) as g_rxd:
+        prx.rx_demod(r_dev, zd_dev, gs)
+    for _ in range(args.warmup):
+        g_rxd.launch(gs)
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a0.record(gs)
+    for _ in range(args.steps):
+        g_rxd.launch(gs)
+    a1.record(gs)
+    torch.cuda.synchronize()
+    rxd_ms = a0.elapsed_time(a1) / args.steps
+    rxd_flops = rxd_cost(rx_all)
+    rx_demod = {"ms": round(rxd_ms, 4), "value": round(rx_samples / (rxd_ms * 1e-3) / 1e6, 1),
+                "unit": "Msamples/s", "achieved_tflops": round(rxd_flops / rxd_ms / 1e9, 2),
+                "frac": round(rxd_flops / rxd_ms / 1e9 / ALU_PEAK_TFLOPS, 4), "algorithmic_flops": int(rxd_flops),
+                "kernel": "fc_rxd_kernel<bf16, N=4096>",
+                "form": "synchronised RX + OFDM demodulation, one short IFFT + one FFT per symbol (Sec. V-A)"}
+    log("rx demod: %.3f ms (%.1f TFLOP/s)" % (rxd_ms, rx_demod["achieved_tflops"]))
 
     # single-unit latency: one slot of the 256 carriers, one RX frame (graph
     # replays, median of 20)
@@ -443,7 +486,7 @@ def main():
                    "storage": "f16 (TX) / bf16 (RX) interleaved I/Q", "timing": "HIP graph replays, HIP events",
                    "tx_samples": tx_samples, "rx_samples": rx_samples, "tx_ms": round(tx_ms, 4),
                    "rx_ms": round(rx_ms, 4), "tuning": tune, "latency": latency},
-        "roofline": roof, "plain": plain, "evm_db": evm, "cpu_baseline": cpu,
+        "roofline": roof, "rx_demod": rx_demod, "plain": plain, "evm_db": evm, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0

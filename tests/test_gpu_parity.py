@@ -162,6 +162,38 @@ def test_adjoint_tiny(name):
     assert_gate(got, ref, "c64", name)
 
 
+# Edge cases: one symbol, a band filling the short transform (K + 2 N_tb = L),
+# the centre bin at either end of its range (|c| + L/2 = N/2), I = 1 at
+# L = N = 2048.
+EDGE = {
+    "one_symbol_sync": [tiny("sync_ola", n_sym=1, ncp=[9])],
+    "one_symbol_cont": [tiny("cont_ols", n_sym=1, ncp=[8])],
+    "full_band": [tiny("sync_ola", L=64, N=256, c=0, K=48, n_tb=8, ncp=[20, 18, 18, 18, 20])],
+    "edge_center_pos": [tiny("sync_ola", L=64, N=256, c=96, K=40, n_tb=8, ncp=[20, 18, 18, 18, 20])],
+    "edge_center_neg": [tiny("sync_ola", L=64, N=256, c=-96, K=40, n_tb=8, ncp=[20, 18, 18, 18, 20])],
+    "i1_2048": [W.subband(15, 1, 1200, 8, 2048, 2048, 0, "cont_ols")],
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+def test_tx_edge(name):
+    got, ref = run_tx(EDGE[name], "c64", seed=17, weights="random")
+    assert_gate(got, ref, "c64", name)
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+def test_rx_edge(name):
+    sbs = [dict(s, mode="sync_ols") if s["mode"].startswith("sync") else s for s in EDGE[name]]
+    got, ref = run_rx(sbs, "c64", seed=19, weights="random")
+    assert_gate(got, ref, "c64", name)
+
+
+@pytest.mark.parametrize("name", [k for k in sorted(EDGE) if EDGE[k][0]["mode"].startswith("sync")])
+def test_rx_demod_edge(name):
+    got, ref = run_rx(EDGE[name], "c64", seed=23, weights="random", demod=True)
+    assert_gate(got, ref, "c64", name)
+
+
 def test_plain_slot_fp32():
     """One 14-symbol slot, continuous OLS, L = 512, N = 2048 (the plain form)."""
     sbs, meta = W.plain_tx_slot()

@@ -262,6 +262,32 @@ def rx_sync(yh, L, N, c, D, ncp, keep_cp=False):
     return np.stack(out)
 
 
+def ofdm_modulate(grid, L, lcp):
+    """CP-OFDM modulation of Sec. III-A with L_OFDM = L: per symbol
+    x_n = sqrt(L) W_L^{-1} X_n, where X_n carries the symbol's K values on
+    subcarriers kappa in [-K/2, K/2) at index kappa mod L, then the last
+    L_CP,n samples prepended (truncated low-rate CP in the synchronised
+    model). grid is (B, K); returns the concatenated low-rate stream."""
+    grid = np.atleast_2d(np.asarray(grid, dtype=complex))
+    B, K = grid.shape
+    Winv = idft_matrix(L)
+    out = []
+    for n in range(B):
+        X = np.zeros(L, dtype=complex)
+        X[np.arange(-K // 2, K // 2) % L] = grid[n]
+        x = np.sqrt(L) * (Winv @ X)
+        out.append(np.r_[x[L - lcp[n]:], x])
+    return np.concatenate(out)
+
+
+def tx_sync_grid(grid, L, N, c, D, ncp):
+    """Synchronised FC TX of a QAM grid: CP-OFDM modulation with the
+    truncated low-rate CP L_CP,n = floor(N_CP,n / I) (Sec. III-E), then
+    tx_sync."""
+    ov = Overlap(L, N, Fraction(1, 2))
+    return tx_sync(ofdm_modulate(grid, L, lowrate_cp(ncp, ov.I, exact=False)), L, N, c, D, ncp)
+
+
 def rx_sync_subcarriers(yh, L, N, c, D, ncp):
     """Symbol-synchronised RX followed by the OFDM demodulation of Sec. IV
     (L_OFDM = L): x_hat_n = (1/sqrt(L)) W_L x_hat_OFDM,n for every symbol, the

@@ -316,6 +316,39 @@ def reduced_vs_direct(fc, seed=7):
     return worst
 
 
+# ----------------------------------------------------- OFDM modulation ----
+def ofdm_round_trip(fc, seed=8):
+    """Demodulating each modulated symbol (CP dropped) with the forward DFT
+    returns the grid on its subcarriers and zeros elsewhere."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for L, K, lcp in ((16, 12, [2, 1, 1]), (64, 40, [5, 4, 4]), (128, 96, [10, 9])):
+        grid = rng.standard_normal((len(lcp), K)) + 1j * rng.standard_normal((len(lcp), K))
+        x = fc.ofdm_modulate(grid, L, lcp)
+        pos = 0
+        for n, l in enumerate(lcp):
+            sym = x[pos + l:pos + l + L]
+            assert np.allclose(x[pos:pos + l], sym[L - l:])            # cyclic prefix
+            X = np.exp(-2j * np.pi * np.outer(np.arange(L), np.arange(L)) / L) @ sym / np.sqrt(L)
+            ref = np.zeros(L, dtype=complex)
+            ref[np.arange(-K // 2, K // 2) % L] = grid[n]
+            worst = max(worst, rel(X, ref))
+            pos += l + L
+    return worst
+
+
+def ofdm_vs_numpy_fft(fc, seed=9):
+    """Cross-check of the dense-matrix modulator against numpy's FFT."""
+    rng = np.random.default_rng(seed)
+    L, K, lcp = 32, 24, [3, 2]
+    grid = rng.standard_normal((2, K)) + 1j * rng.standard_normal((2, K))
+    X = np.zeros((2, L), dtype=complex)
+    X[:, np.arange(-K // 2, K // 2) % L] = grid
+    xs = np.fft.ifft(X, axis=1) * np.sqrt(L)
+    ref = np.concatenate([np.r_[xs[n][L - lcp[n]:], xs[n]] for n in range(2)])
+    return rel(fc.ofdm_modulate(grid, L, lcp), ref)
+
+
 ALL_PINS = {
     "pr1_sync": lambda fc: pr1_sync(fc),
     "pr1_cont_ols": lambda fc: pr1_cont(fc, False),
@@ -340,5 +373,7 @@ ALL_PINS = {
     "concat_vs_keepcp": lambda fc: concat_sync_vs_keepcp(fc),
     "tone_rx_subcarriers": lambda fc: tone_rx_subcarriers(fc),
     "reduced_vs_direct": lambda fc: reduced_vs_direct(fc),
+    "ofdm_round_trip": lambda fc: ofdm_round_trip(fc),
+    "ofdm_vs_numpy_fft": lambda fc: ofdm_vs_numpy_fft(fc),
 }
 TOL = 1e-10

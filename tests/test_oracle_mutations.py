@@ -51,6 +51,12 @@ MUTATIONS = {
     "reduced_block_swap": ("for g0, g1 in g:", "for g1, g0 in g:"),
     "blocks_freq_no_phase": ("g.append(phi_r * th_n * (Gf @ wn[r * N // 2:r * N // 2 + N]) / np.sqrt(ov.I))",
                              "g.append(th_n * (Gf @ wn[r * N // 2:r * N // 2 + N]) / np.sqrt(ov.I))"),
+    "ofdm_no_scale": ("x = np.sqrt(L) * (Winv @ X)", "x = Winv @ X"),
+    "ofdm_forward": ("x = np.sqrt(L) * (Winv @ X)", "x = (dft_matrix(L) @ X) / np.sqrt(L)"),
+    "ofdm_cp_from_start": ("out.append(np.r_[x[L - lcp[n]:], x])\n    return np.concatenate(out)\n\n\ndef tx_sync_grid",
+                           "out.append(np.r_[x[:lcp[n]], x])\n    return np.concatenate(out)\n\n\ndef tx_sync_grid"),
+    "ofdm_subcarrier_shift": ("X[np.arange(-K // 2, K // 2) % L] = grid[n]\n        x = np.sqrt(L)",
+                              "X[np.arange(-K // 2 + 1, K // 2 + 1) % L] = grid[n]\n        x = np.sqrt(L)"),
     "blocks_freq_theta_sign": ("th_n = np.conj(unit_phase(c * sigma[n], N))", "th_n = unit_phase(c * sigma[n], N)"),
 }
 

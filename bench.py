@@ -90,6 +90,13 @@ def tx_input(plan, sbs, meta):
     return xs
 
 
+def tx_grids(sbs, meta):
+    """The QAM grids behind tx_input (same seed, same draw order)."""
+    import fcsynth
+    rng = np.random.default_rng(meta["seed"])
+    return [fcsynth.qam_grid(rng, meta["qam"], s["n_symbols"], s["n_active"]) for s in sbs]
+
+
 def rx_input(plan, sbs, meta):
     """One frame: the 8 subbands' 256-QAM CP-OFDM from one 4096-point IDFT per
     symbol, placed where the plan expects the first useful sample, plus AWGN."""
@@ -281,7 +288,7 @@ def main():
               file=sys.stderr)
         return 2
     import torch
-    from paper_2008_00672_amd import Graph, Plan, OP_RX, OP_RXD, OP_TX
+    from paper_2008_00672_amd import Graph, Plan, OP_RX, OP_RXD, OP_TX, OP_TXG
 
     if args.copy_calib:
         n = 256 << 20
@@ -325,7 +332,7 @@ def main():
     # TX call and one RX call captured as HIP graphs on a side stream
     gs = torch.cuda.Stream()
     torch.cuda.synchronize()
-    rl = rc = 0
+    tl = tc = rl = rc = 0
     if args.tuning:
         tl, tc, rl, rc = [int(v) for v in args.tuning.split(",")]
         ptx.set_tuning(OP_TX, tl, tc)
@@ -393,6 +400,35 @@ def main():
                 "kernel": "fc_rxd_kernel<bf16, N=4096>",
                 "form": "synchronised RX + OFDM demodulation, one short IFFT + one FFT per symbol (Sec. V-A)"}
     log("rx demod: %.3f ms (%.1f TFLOP/s)" % (rxd_ms, rx_demod["achieved_tflops"]))
+
+    # the grid-input TX (QAM grid -> OFDM IFFT + truncated CP -> FC in the
+    # kernels) on the same TX workload, outside the step
+    g_in = to_dev(np.concatenate([g.ravel() for g in tx_grids(tx_one, tx_meta)]), "f16", reps=args.tx_batches)
+    y_g = ptx.empty(int(hi[-1]))
+    if args.tuning:
+        ptx.set_tuning(OP_TXG, tl, tc)
+        tune["tx_grid"] = ptx.get_tuning(OP_TXG)
+    else:
+        tune["tx_grid"] = ptx.autotune(OP_TXG, g_in, y_g, stream=gs)
+    with Graph(gs) as g_txg:
+        ptx.tx_grid(g_in, y_g, gs)
+    for _ in range(args.warmup):
+        g_txg.launch(gs)
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a0.record(gs)
+    for _ in range(args.steps):
+        g_txg.launch(gs)
+    a1.record(gs)
+    torch.cuda.synchronize()
+    txg_ms = a0.elapsed_time(a1) / args.steps
+    txg_flops = tx_flops + sum(2 * s["n_symbols"] * 5 * s["n_short"] * math.log2(s["n_short"]) for s in tx_all)
+    tx_grid = {"ms": round(txg_ms, 4), "value": round(tx_samples / (txg_ms * 1e-3) / 1e6, 1), "unit": "Msamples/s",
+               "achieved_tflops": round(txg_flops / txg_ms / 1e9, 2),
+               "frac": round(txg_flops / txg_ms / 1e9 / ALU_PEAK_TFLOPS, 4), "algorithmic_flops": int(txg_flops),
+               "form": "QAM grid in (FP16): OFDM IFFT + truncated CP + synchronised FC TX in the kernels "
+                       "(the OFDM IFFT is run for each of a symbol's two blocks)"}
+    log("tx grid: %.3f ms (%.1f TFLOP/s)" % (txg_ms, tx_grid["achieved_tflops"]))
 
     # single-unit latency: one slot of the 256 carriers, one RX frame (graph
     # replays, median of 20)
@@ -486,7 +522,7 @@ def main():
                    "storage": "f16 (TX) / bf16 (RX) interleaved I/Q", "timing": "HIP graph replays, HIP events",
                    "tx_samples": tx_samples, "rx_samples": rx_samples, "tx_ms": round(tx_ms, 4),
                    "rx_ms": round(rx_ms, 4), "tuning": tune, "latency": latency},
-        "roofline": roof, "rx_demod": rx_demod, "plain": plain, "evm_db": evm, "cpu_baseline": cpu,
+        "roofline": roof, "rx_demod": rx_demod, "tx_grid": tx_grid, "plain": plain, "evm_db": evm, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -68,7 +68,8 @@ enum {
   FC_OP_TX = 0,      /* fc_tx_synthesize: low-rate CP-OFDM in, high-rate out            */
   FC_OP_RX = 1,      /* fc_rx_analyze:    high-rate in, low-rate out                    */
   FC_OP_ADJ = 2,     /* fc_tx_adjoint:    high-rate in, low-rate CP-OFDM-shaped out     */
-  FC_OP_RXD = 3      /* fc_rx_demodulate: high-rate in, subcarriers out (synchronised)   */
+  FC_OP_RXD = 3,     /* fc_rx_demodulate: high-rate in, subcarriers out (synchronised)   */
+  FC_OP_TXG = 4      /* fc_tx_modulate:   QAM grid in, high-rate out (synchronised OLA)  */
 };
 
 /*
@@ -139,7 +140,8 @@ fc_status fc_plan_counts(const fc_plan* plan, int32_t* n_sb, int32_t* n_streams)
  * Low-rate layout: FC_OP_TX / FC_OP_ADJ and continuous FC_OP_RX use the
  * concatenated CP-OFDM symbols (sum_n n_short + L_CP,n); synchronised FC_OP_RX
  * returns n_symbols * n_short samples (CP removed, Sec. IV concatenation), and
- * FC_OP_RXD n_symbols * n_short subcarrier values.
+ * FC_OP_RXD n_symbols * n_short subcarrier values, FC_OP_TXG (input) the
+ * QAM grid, n_symbols * n_active values.
  * Either pointer may be NULL.
  */
 fc_status fc_plan_layout(const fc_plan* plan, int32_t op, int64_t* lowrate_off,
@@ -191,6 +193,21 @@ fc_status fc_tx_synthesize(fc_plan* plan, const void* lowrate_in, void* highrate
  * symbol and return the CP-free symbols (Sec. IV concatenation).
  */
 fc_status fc_rx_analyze(fc_plan* plan, const void* highrate_in, void* lowrate_out, void* stream);
+
+/*
+ * CP-OFDM modulation and synchronised FC synthesis in one pass (Sec. III-A
+ * modulation with L_OFDM = n_short and the truncated low-rate CP of
+ * Sec. III-E, then the Sec. III-C/D synthesis): the kernels run each symbol's
+ * L-point IFFT in LDS and take the FC blocks from it, so the low-rate
+ * CP-OFDM signal never goes to memory.
+ *   grid_in       device, FC_OP_TXG layout: per subband n_symbols rows of
+ *                 n_active values (subcarriers kappa = -K/2 .. K/2-1), the
+ *                 plan's I/O type; x_n = sqrt(L) W_L^{-1} X_n.
+ *   highrate_out  device, high-rate layout, as fc_tx_synthesize.
+ * Every subband must be FC_SYNC_OLA, else FC_E_STATE. Asynchronous on
+ * `stream`; errors as fc_tx_synthesize.
+ */
+fc_status fc_tx_modulate(fc_plan* plan, const void* grid_in, void* highrate_out, void* stream);
 
 /*
  * Synchronised FC analysis followed by OFDM demodulation (Sec. IV, with
@@ -245,7 +262,7 @@ fc_status fc_plan_stats(const fc_plan* plan, int32_t op, int64_t* n_blocks, int6
                         int64_t* n_launches);
 
 /*
- * Tuning of operation op (FC_OP_TX, FC_OP_RX, FC_OP_ADJ, FC_OP_RXD; FC_OP_ADJ also sets
+ * Tuning of operation op (FC_OP_TX .. FC_OP_TXG; FC_OP_ADJ also sets
  * the weight gradient's work split):
  *   run_len  FC blocks per workgroup task (consecutive blocks of one group;
  *            0 = the planner's choice from the total block count; TX runs of

@@ -6,7 +6,7 @@ this package does not load the library, the first call does, and it raises if
 the library has not been built.
 """
 from .fc import (Plan, Graph, FcError, lib, CONT_OLA, CONT_OLS, SYNC_OLA, SYNC_OLS,  # noqa: F401
-                 OP_TX, OP_RX, OP_ADJ, OP_RXD)
+                 OP_TX, OP_RX, OP_ADJ, OP_RXD, OP_TXG)
 
 
 def fc_tx(plan, x, w):

@@ -400,8 +400,52 @@ template <int IO, int NT, int P> struct LoadAhead : NoPrefetch {
       }
     }
   }
+  // The first pass of an L-point IFFT of one QAM symbol: bin i carries grid
+  // value kappa + K/2 for kappa = i (i < K/2) or i - P (i >= P - K/2), else 0.
+  __device__ __forceinline__ void issue_grid(const T* row, int K, int tid) {
+    asm volatile("" : "+v"(tid) : : "memory");
+    valid = 0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      int i, b;
+      if (first_pos<NT, P, 0>(s, tid, i, b)) {
+        const int g = i < (K >> 1) ? i + (K >> 1) : (i >= P - (K >> 1) ? i - P + (K >> 1) : -1);
+        if (g >= 0) {
+          raw[s] = row[g];
+          valid |= 1u << s;
+        }
+      }
+    }
+  }
   __device__ __forceinline__ float2 operator()(int slot, int, int, int) const {
     return (valid >> slot) & 1u ? Io<IO>::ld(raw, slot) : make_float2(0.f, 0.f);
+  }
+};
+
+// The same mapping without prefetch (one grid row of an L-point symbol).
+template <int IO, int L> struct LoadGridRow : NoPrefetch {
+  const typename Io<IO>::T* row; int K;
+  __device__ __forceinline__ float2 operator()(int, int i, int, int) const {
+    const int g = i < (K >> 1) ? i + (K >> 1) : (i >= L - (K >> 1) ? i - L + (K >> 1) : -1);
+    return g >= 0 ? Io<IO>::ld(row, g) : make_float2(0.f, 0.f);
+  }
+};
+
+// Last pass of the OFDM IFFT: x[t] = IFFT(X)[t] / sqrt(L), natural order.
+struct StoreScaled : NoPrefetch {
+  float2* buf; float scale;
+  __device__ __forceinline__ void operator()(int, int, float2 v, int tp) const {
+    buf[tp] = make_float2(v.x * scale, v.y * scale);
+  }
+};
+
+// First pass of the FC short FFT of a symbol-synchronised block taken from the
+// OFDM symbol in LDS: block sample i in the window [lo, hi) is OFDM sample
+// (i + shift) mod L (the CP and the zero padding are index ranges).
+template <int L> struct LoadCyclic : NoPrefetch {
+  const float2* x; int lo, hi, shift;
+  __device__ __forceinline__ float2 operator()(int, int i, int, int) const {
+    return (i >= lo && i < hi) ? x[pad((i + shift) & (L - 1))] : make_float2(0.f, 0.f);
   }
 };
 
@@ -578,7 +622,7 @@ __device__ __forceinline__ void zero_span(void* out, int64_t lo, int64_t hi) {
 // band region, then the workgroup runs the group's long IFFTs and epilogues
 // in block order (the OLA carry passes from block to block through LDS).
 // Larger L: one block at a time, the short FFT on the whole workgroup.
-template <int IO, int L, int LOGI>
+template <int IO, int L, int LOGI, bool FRONT>
 __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void fc_tx_pruned_kernel(LaunchArgs a) {
   constexpr int N = L << LOGI;
   constexpr bool kWaveShort = L <= 1024;
@@ -617,7 +661,8 @@ __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void
   LoadAhead<IO, NTS, L> ld;
   if (wave < NB && wave < T.blk_count) {
     const BlockSb Z0 = a.bsb[a.blk[T.blk_first + wave].bs];
-    ld.issue(at<IO>(a.in, Z0.x0), Z0.lo, Z0.hi, sid);
+    if constexpr (FRONT) ld.issue_grid(at<IO>(a.in, Z0.x0), Z0.K, sid);
+    else ld.issue(at<IO>(a.in, Z0.x0), Z0.lo, Z0.hi, sid);
   }
   LoadPruned<kThreads, L, LOGI> lp;
   lp.tw = tw; lp.q0 = S.q0;
@@ -629,12 +674,25 @@ __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void
       const BlockSb Zw = a.bsb[a.blk[T.blk_first + g0 + wave].bs];
       StoreBand<NTS, L> sb;
       sb.V = band; sb.D = D; sb.ph = make_float2(Zw.ph.x, Zw.ph.y); sb.c = S.c;
-      fft_run<NTS, L, 0, -1>(band, sid, ld, sb, twb);
+      if constexpr (FRONT) {
+        // grid input: the symbol's OFDM IFFT in the band region, then the
+        // block's short FFT from it
+        StoreScaled sx;
+        sx.buf = band; sx.scale = rsqrtf((float)L);
+        fft_run<NTS, L, 0, +1>(band, sid, ld, sx, twb);
+        group_sync<NTS>();
+        LoadCyclic<L> lcy;
+        lcy.x = band; lcy.lo = Zw.lo; lcy.hi = Zw.hi; lcy.shift = Zw.shift;
+        fft_run<NTS, L, 0, -1>(band, sid, lcy, sb, twb);
+      } else {
+        fft_run<NTS, L, 0, -1>(band, sid, ld, sb, twb);
+      }
     }
     // start loading the next group's inputs while this group's IFFTs run
     if (wave < NB && g0 + NB + wave < T.blk_count) {
       const BlockSb Zn = a.bsb[a.blk[T.blk_first + g0 + NB + wave].bs];
-      ld.issue(at<IO>(a.in, Zn.x0), Zn.lo, Zn.hi, sid);
+      if constexpr (FRONT) ld.issue_grid(at<IO>(a.in, Zn.x0), Zn.K, sid);
+      else ld.issue(at<IO>(a.in, Zn.x0), Zn.lo, Zn.hi, sid);
     }
     for (int k = 0; k < nb; ++k) {
       const int bi = g0 + k;
@@ -662,7 +720,7 @@ __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void
 // Several subbands share the long IFFT: their weighted bands are added into
 // one N-bin spectrum, then a full N-point IFFT. Short FFTs are dispatched by
 // size in separate loops (one region per size keeps register use low).
-template <int IO, int NL>
+template <int IO, int NL, bool FRONT>
 __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int lmax) {
   extern __shared__ float2 smem[];
   const int task = blockIdx.x;
@@ -693,12 +751,24 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL) continue;
           const BlockSb Z = a.bsb[B.bs + m];
-          LoadSeg<IO> ld;
-          ld.x = at<IO>(a.in, Z.x0); ld.lo = Z.lo; ld.hi = Z.hi;
           StoreAddLong<NL> st;
           st.S = S; st.D = a.weights + Sb.w_off; st.ph = make_float2(Z.ph.x, Z.ph.y); st.L = LL; st.q0 = Sb.q0;
           __syncthreads();
-          fft_run<kThreads, LL, 0, -1>(bs, tid, ld, st, tw);
+          if constexpr (FRONT) {
+            LoadGridRow<IO, LL> lg;
+            lg.row = at<IO>(a.in, Z.x0); lg.K = Z.K;
+            StoreScaled sx;
+            sx.buf = bs; sx.scale = rsqrtf((float)LL);
+            fft_run<kThreads, LL, 0, +1>(bs, tid, lg, sx, tw);
+            __syncthreads();
+            LoadCyclic<LL> lcy;
+            lcy.x = bs; lcy.lo = Z.lo; lcy.hi = Z.hi; lcy.shift = Z.shift;
+            fft_run<kThreads, LL, 0, -1>(bs, tid, lcy, st, tw);
+          } else {
+            LoadSeg<IO> ld;
+            ld.x = at<IO>(a.in, Z.x0); ld.lo = Z.lo; ld.hi = Z.hi;
+            fft_run<kThreads, LL, 0, -1>(bs, tid, ld, st, tw);
+          }
         }
       }
     };
@@ -1097,7 +1167,13 @@ hipError_t launch_pruned(const LaunchArgs& a, int logi, size_t lds, hipStream_t 
   dim3 block(kThreads);
   switch (logi) {
 #define FC_LI(LI) \
-  case LI: if constexpr ((L << LI) <= kMaxPoints) { hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI>), grid, block, lds, s, a); return hipGetLastError(); } break;
+  case LI:                                                                                          \
+    if constexpr ((L << LI) <= kMaxPoints) {                                                        \
+      if (a.front) hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI, true>), grid, block, lds, s, a); \
+      else hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI, false>), grid, block, lds, s, a);     \
+      return hipGetLastError();                                                                     \
+    }                                                                                               \
+    break;
     FC_LI(1) FC_LI(2) FC_LI(3) FC_LI(4) FC_LI(5) FC_LI(6) FC_LI(7) FC_LI(8)
 #undef FC_LI
     default: break;
@@ -1110,7 +1186,8 @@ hipError_t launch_size(int cls, const LaunchArgs& a, int aux, size_t lds, hipStr
   dim3 block(kThreads);
   if (cls == 0) return launch_pruned<IO, SZ>(a, aux, lds, s, grid);
   if (cls == 1) {
-    hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ>), grid, block, lds, s, a, aux);
+    if (a.front) hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ, true>), grid, block, lds, s, a, aux);
+    else hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ, false>), grid, block, lds, s, a, aux);
   } else if (cls == 3) {
     hipLaunchKernelGGL((fc_wgrad_kernel<IO, SZ>), grid, block, lds, s, a, aux);
   } else if (cls == 4) {
@@ -1146,9 +1223,12 @@ hipError_t lds_limit_pruned(size_t bytes) {
   hipError_t e = hipSuccess;
 #define FC_LI(LI)                                                                                   \
   if constexpr ((L << LI) <= kMaxPoints) {                                                          \
-    hipError_t r = hipFuncSetAttribute((const void*)fc_tx_pruned_kernel<IO, L, LI>,                 \
+    hipError_t r = hipFuncSetAttribute((const void*)fc_tx_pruned_kernel<IO, L, LI, false>,          \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);     \
+    hipError_t rf = hipFuncSetAttribute((const void*)fc_tx_pruned_kernel<IO, L, LI, true>,          \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
     if (r != hipSuccess) e = r;                                                                     \
+    if (rf != hipSuccess) e = rf;                                                                   \
   }
   FC_LI(1) FC_LI(2) FC_LI(3) FC_LI(4) FC_LI(5) FC_LI(6) FC_LI(7) FC_LI(8)
 #undef FC_LI
@@ -1161,8 +1241,11 @@ hipError_t lds_limits_io(size_t bytes) {
 #define FC_SZ(SZ)                                                                                   \
   {                                                                                                 \
     hipError_t r1 = lds_limit_pruned<IO, SZ>(bytes);                                                \
-    hipError_t r2 = hipFuncSetAttribute((const void*)fc_tx_full_kernel<IO, SZ>,                     \
+    hipError_t r2 = hipFuncSetAttribute((const void*)fc_tx_full_kernel<IO, SZ, false>,              \
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
+    hipError_t r2f = hipFuncSetAttribute((const void*)fc_tx_full_kernel<IO, SZ, true>,              \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);   \
+    if (r2f != hipSuccess) e = r2f;                                                                 \
     hipError_t r3 = hipFuncSetAttribute((const void*)fc_rx_kernel<IO, SZ>,                          \
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
     hipError_t r4 = hipFuncSetAttribute((const void*)fc_wgrad_kernel<IO, SZ>,                       \

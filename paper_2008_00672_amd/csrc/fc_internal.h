@@ -110,9 +110,12 @@ struct BlockDesc {
 
 // Per (block, subband).
 struct BlockSb {
-  int64_t x0;                // low-rate element index (absolute) of block sample 0
+  int64_t x0;                // low-rate element index (absolute) of block sample 0;
+                             // grid-input TX: first grid value of the block's symbol
   int32_t lo, hi;            // TX: valid input window; RX: low-rate keep window
   Cf ph;                     // TX: sqrt(I)/N * phi_r theta_n; RX: conj(phi_r theta_n)/(sqrt(I) L)
+  int32_t shift;             // grid-input TX: block sample i is OFDM sample (i + shift) mod L
+  int32_t K;                 // grid-input TX: active subcarriers of the subband
 };
 
 // A unit of work: a run of consecutive blocks of one group.
@@ -143,6 +146,7 @@ struct LaunchArgs {
   const void* in;
   void* out;
   const void* in2;           // weight gradient: the forward low-rate input
+  int32_t front;             // TX: 1 = input is the QAM grid (OFDM modulation in the kernel)
 };
 
 }  // namespace fcx

@@ -114,9 +114,9 @@ struct fc_plan {
   float* d_w = nullptr;
   Cf* d_tw = nullptr;
   Cf* d_twp = nullptr;           // per-pass twiddle bases
-  Op op[4];
-  int run_len[4] = {0, 0, 0, 0}; // blocks per task per op (0: planner heuristic)
-  int conc[4] = {kMaxConc, kMaxConc, kMaxConc, kMaxConc};   // per op: launches of one independent set in flight
+  Op op[5];
+  int run_len[5] = {0, 0, 0, 0, 0};   // blocks per task per op (0: planner heuristic)
+  int conc[5] = {kMaxConc, kMaxConc, kMaxConc, kMaxConc, kMaxConc};   // per op: launches of one independent set in flight
   hipStream_t side[kMaxConc - 1] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kMaxConc - 1] = {};
@@ -238,17 +238,20 @@ void build_op(fc_plan* P, int kind) {
   op = Op();
   const int nsb = (int)P->subs.size();
   // validity: TX needs CONT_* or SYNC_OLA; ADJ likewise; RX any; the
-  // demodulating RX needs synchronised subbands
+  // demodulating RX needs synchronised subbands; the grid-input TX SYNC_OLA
   for (const Sub& s : P->subs) {
     if ((kind == 0 || kind == 2) && s.d.mode == FC_SYNC_OLS) return;
     if (kind == 3 && !s.sync) return;
+    if (kind == 4 && s.d.mode != FC_SYNC_OLA) return;
   }
   op.valid = true;
+  const int tk = kind == 4 ? 0 : kind;         // the grid-input TX is scheduled as the TX
   // low-rate layout
   op.lo_off.assign(nsb + 1, 0);
   for (int m = 0; m < nsb; ++m) {
     const Sub& s = P->subs[m];
-    const int64_t len = ((kind == 1 || kind == 3) && s.sync) ? (int64_t)s.d.n_symbols * s.L : s.n_in;
+    const int64_t len = kind == 4 ? (int64_t)s.d.n_symbols * s.d.n_active
+                        : ((kind == 1 || kind == 3) && s.sync) ? (int64_t)s.d.n_symbols * s.L : s.n_in;
     op.lo_off[m + 1] = op.lo_off[m] + len;
   }
   // processing groups of this operation: the plan's groups, except that an RX
@@ -258,7 +261,7 @@ void build_op(fc_plan* P, int kind) {
   std::vector<OpGroup> ogroups;
   for (size_t g = 0; g < P->groups.size(); ++g) {
     const Group& G = P->groups[g];
-    if (kind == 0) { ogroups.push_back(OpGroup{(int)g, G.subs}); continue; }
+    if (tk == 0) { ogroups.push_back(OpGroup{(int)g, G.subs}); continue; }
     // RX: split so that each part's subband regions fit kRxMaxLds LDS entries
     // and no long bin feeds more than kRxMaxDest of its subbands
     OpGroup cur{(int)g, {}};
@@ -289,7 +292,7 @@ void build_op(fc_plan* P, int kind) {
     gd.N = G.N; gd.logN = ilog2(G.N);
     gd.n_sb = (int)OG.subs.size(); gd.sb_first = (int)op.sb.size();
     const Sub& s0 = P->subs[OG.subs[0]];
-    gd.prune = (kind == 0 && OG.subs.size() == 1 && s0.I >= 2 && s0.L >= 16) ? 1 : 0;
+    gd.prune = (tk == 0 && OG.subs.size() == 1 && s0.I >= 2 && s0.L >= 16) ? 1 : 0;
     op.grp.push_back(gd);
     int cofs = 0;
     for (int m : OG.subs) {
@@ -304,7 +307,7 @@ void build_op(fc_plan* P, int kind) {
       d.lo_off = op.lo_off[m]; d.lo_len = op.lo_off[m + 1] - op.lo_off[m];
       op.sb.push_back(d);
     }
-    if (kind != 0) {
+    if (tk != 0) {
       GroupDesc& gr = op.grp.back();
       // scatter map: long bin q feeds IFFT input u = (p + L/2) mod L of every
       // subband with p = (q - q0) mod N < L, at LDS cofs + pad(u)
@@ -381,7 +384,7 @@ void build_op(fc_plan* P, int kind) {
       else t_local = (int64_t)b * s0.NS;
       bd.t0 = base + t_local;
       // high-rate window
-      if (kind == 0) {
+      if (tk == 0) {
         if (!G.sync && !G.ola) { bd.hlo = (int)s0.NL; bd.hhi = (int)(s0.NL + s0.NS); }
         else { bd.hlo = 0; bd.hhi = N; }
       } else {
@@ -416,7 +419,7 @@ void build_op(fc_plan* P, int kind) {
           phase_num = (int64_t)r * s.d.center_bin * s.LS * s.I;   // r c L_S / L in units of 1/N
           const int64_t xrel = (int64_t)r * s.LS - s.LO;
           bool low_window;      // TX input window a / RX keep window a, else full block
-          if (kind == 0) low_window = G.ola;
+          if (tk == 0) low_window = G.ola;
           else if (kind == 1) low_window = !G.ola;           // G^(OLS) keeps [L_L, L_L + L_S)
           else low_window = G.ola;                           // adjoint of TX-OLA: keep a
           w = low_window ? clip_valid(s, xrel, s.LL, s.LL + s.LS, s.n_in)
@@ -424,14 +427,21 @@ void build_op(fc_plan* P, int kind) {
         }
         z.x0 = op.lo_off[m] + w.x0;
         z.lo = w.lo; z.hi = w.hi;
-        if (kind == 0) z.ph = unit_phase(phase_num, N, std::sqrt((double)s.I) / N);
+        if (kind == 4) {
+          // block sample i of z = [0_{S_L}; x_CP; 0_{L_T}] at r L/2 is OFDM sample
+          // (r L/2 + i - L/4) mod L of the symbol (S_L + L_CP,n = L/4)
+          z.x0 = op.lo_off[m] + (int64_t)n * s.d.n_active;
+          z.shift = r ? L / 4 : 3 * L / 4;
+          z.K = s.d.n_active;
+        }
+        if (tk == 0) z.ph = unit_phase(phase_num, N, std::sqrt((double)s.I) / N);
         else if (kind == 3) z.ph = unit_phase(-phase_num, N, 1.0 / std::sqrt((double)s.I));   // g^(r) itself
         else z.ph = unit_phase(-phase_num, N, 1.0 / (std::sqrt((double)s.I) * L));
         op.bsb.push_back(z);
       }
     }
     const int64_t span_lo = base, span_hi = base + G.Q;
-    if (kind == 0) {
+    if (tk == 0) {
       // --- TX runs ---
       const bool acc = P->groups.size() > 1 &&
           std::count_if(P->groups.begin(), P->groups.end(), [&](const Group& o) { return o.stream == G.stream; }) > 1;
@@ -535,7 +545,7 @@ void build_op(fc_plan* P, int kind) {
       op.phases.push_back(p);
     }
   };
-  if (kind == 0) {
+  if (tk == 0) {
     if (any_acc_tx) op.phases.push_back(Op::Phase{2, 0, 0, 0, 0, P->hi_off.back(), 0, 0, 0, -1, 0});
     // groups of one rank belong to different streams: their launches are independent
     for (auto& kv : tx_phase) emit(kv.second, true, kv.first);
@@ -575,6 +585,7 @@ hipError_t launch_phase(fc_plan* P, const Op& op, const Op::Phase& ph, const voi
   a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
   a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
   a.in = in; a.out = out;
+  a.front = &op == &P->op[FC_OP_TXG] ? 1 : 0;
   return launch_kernel(ph.cls, ph.size, a, ph.aux, ph.lds, st);
 }
 
@@ -765,7 +776,7 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   P->w_off.resize(n_sb);
   for (int m = 0; m < n_sb; ++m) { P->w_off[m] = P->w_total; P->w_total += P->subs[m].L; }
   // host tables
-  for (int k = 0; k < 4; ++k) build_op(P, k);
+  for (int k = 0; k < 5; ++k) build_op(P, k);
   if (device < 0) {        // host-only plan: schedules and layouts, no device state
     *plan = P;
     return FC_OK;
@@ -801,9 +812,9 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   if (!st) st = upload(tw, &P->d_tw);
   if (!st) st = upload(twp, &P->d_twp);
   if (!st) st = upload(w, &P->d_w);
-  for (int k = 0; k < 4 && !st; ++k) st = upload_op(P->op[k]);
+  for (int k = 0; k < 5 && !st; ++k) st = upload_op(P->op[k]);
   size_t lds_max = 0;
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < 5; ++k)
     for (auto& ph : P->op[k].phases) lds_max = std::max(lds_max, std::max(ph.lds, ph.glds));
   if (!st && lds_max > 65536 && set_lds_limits(lds_max) != hipSuccess) st = FC_E_UNSUPPORTED;
   // side streams (default priority) and fork/join events
@@ -829,7 +840,7 @@ void fc_plan_destroy(fc_plan* P) {
     if (P->ev_join[q]) (void)hipEventDestroy(P->ev_join[q]);
   }
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
-  for (int k = 0; k < 4; ++k) free_op(P->op[k]);
+  for (int k = 0; k < 5; ++k) free_op(P->op[k]);
   (void)hipFree(P->d_w);
   (void)hipFree(P->d_tw);
   (void)hipFree(P->d_twp);
@@ -845,7 +856,7 @@ fc_status fc_plan_counts(const fc_plan* P, int32_t* n_sb, int32_t* n_streams) {
 }
 
 fc_status fc_plan_layout(const fc_plan* P, int32_t op, int64_t* lowrate_off, int64_t* highrate_off) {
-  if (!P || op < FC_OP_TX || op > FC_OP_RXD) return FC_E_ARG;
+  if (!P || op < FC_OP_TX || op > FC_OP_TXG) return FC_E_ARG;
   const Op& o = P->op[op];
   if (!o.valid) return FC_E_STATE;
   if (lowrate_off) std::copy(o.lo_off.begin(), o.lo_off.end(), lowrate_off);
@@ -913,7 +924,7 @@ fc_status fc_get_weights(const fc_plan* P, int32_t sb, float* w_host, int32_t n)
 }
 
 fc_status fc_plan_set_tuning(fc_plan* P, int32_t op, int32_t run_len, int32_t conc) {
-  if (!P || op < 0 || op > 3 || run_len < 0 || run_len > 256 || conc < 1 || conc > kMaxConc) return FC_E_ARG;
+  if (!P || op < 0 || op > 4 || run_len < 0 || run_len > 256 || conc < 1 || conc > kMaxConc) return FC_E_ARG;
   if (!P->op[op].valid) return FC_E_STATE;
   if (P->device >= 0) {
     int cur = -1;
@@ -931,7 +942,7 @@ fc_status fc_plan_set_tuning(fc_plan* P, int32_t op, int32_t run_len, int32_t co
 }
 
 fc_status fc_plan_get_tuning(const fc_plan* P, int32_t op, int32_t* run_len, int32_t* conc) {
-  if (!P || op < 0 || op > 3) return FC_E_ARG;
+  if (!P || op < 0 || op > 4) return FC_E_ARG;
   if (run_len) *run_len = P->run_len[op];
   if (conc) *conc = P->conc[op];
   return FC_OK;
@@ -939,12 +950,12 @@ fc_status fc_plan_get_tuning(const fc_plan* P, int32_t op, int32_t* run_len, int
 
 fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, void* stream, int32_t* best_run_len,
                            int32_t* best_conc, float* best_ms) {
-  if (!P || op < 0 || op > 3 || !in || !out) return FC_E_ARG;
+  if (!P || op < 0 || op > 4 || !in || !out) return FC_E_ARG;
   if (!P->op[op].valid || P->device < 0) return FC_E_STATE;
   const hipStream_t st = (hipStream_t)stream;
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
-  const std::vector<int> lens = op == FC_OP_TX    ? std::vector<int>{0, 8, 16, 32, 64}
+  const std::vector<int> lens = (op == FC_OP_TX || op == FC_OP_TXG) ? std::vector<int>{0, 8, 16, 32, 64}
                                : op == FC_OP_RXD ? std::vector<int>{0, 2, 4, 8, 16}
                                                  : std::vector<int>{0, 1, 2, 4, 8, 16};
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -985,7 +996,7 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
 }
 
 fc_status fc_plan_stats(const fc_plan* P, int32_t op, int64_t* n_blocks, int64_t* n_tasks, int64_t* n_launches) {
-  if (!P || op < FC_OP_TX || op > FC_OP_RXD) return FC_E_ARG;
+  if (!P || op < FC_OP_TX || op > FC_OP_TXG) return FC_E_ARG;
   const Op& o = P->op[op];
   if (!o.valid) return FC_E_STATE;
   if (n_blocks) *n_blocks = (int64_t)o.blk.size();
@@ -1002,6 +1013,11 @@ fc_status fc_tx_synthesize(fc_plan* P, const void* in, void* out, void* stream) 
 fc_status fc_rx_analyze(fc_plan* P, const void* in, void* out, void* stream) {
   if (!P) return FC_E_ARG;
   return run_op(P, FC_OP_RX, in, out, (hipStream_t)stream);
+}
+
+fc_status fc_tx_modulate(fc_plan* P, const void* grid_in, void* out, void* stream) {
+  if (!P) return FC_E_ARG;
+  return run_op(P, FC_OP_TXG, grid_in, out, (hipStream_t)stream);
 }
 
 fc_status fc_rx_demodulate(fc_plan* P, const void* in, void* out, void* stream) {

@@ -17,7 +17,7 @@ CONT_OLA, CONT_OLS, SYNC_OLA, SYNC_OLS = 0, 1, 2, 3
 MODES = {"cont_ola": CONT_OLA, "cont_ols": CONT_OLS, "sync_ola": SYNC_OLA, "sync_ols": SYNC_OLS}
 IO_C64, IO_F16, IO_BF16 = 0, 1, 2
 IOS = {"c64": IO_C64, "f16": IO_F16, "bf16": IO_BF16}
-OP_TX, OP_RX, OP_ADJ, OP_RXD = 0, 1, 2, 3
+OP_TX, OP_RX, OP_ADJ, OP_RXD, OP_TXG = 0, 1, 2, 3, 4
 
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -47,6 +47,7 @@ EXPORTS = {
     "fc_rx_analyze": (_I32, [_P, _P, _P, _P]),
     "fc_tx_adjoint": (_I32, [_P, _P, _P, _P]),
     "fc_rx_demodulate": (_I32, [_P, _P, _P, _P]),
+    "fc_tx_modulate": (_I32, [_P, _P, _P, _P]),
     "fc_tx_weight_grad": (_I32, [_P, _P, _P, _P, _P]),
     "fc_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
     "fc_plan_get_tuning": (_I32, [_P, _I32, _I32P, _I32P]),
@@ -234,6 +235,17 @@ class Plan:
         _check(lib().fc_rx_analyze(self._h, _ptr(y), _ptr(out), _stream_handle(stream)), "fc_rx_analyze")
         return out
 
+    def tx_grid(self, grid, out=None, stream=None):
+        """CP-OFDM modulation + synchronised FC TX of QAM grids (per subband
+        n_symbols x n_active values, concatenated in plan order)."""
+        lo, hi = self.layout(OP_TXG)
+        self._check_buf(grid, int(lo[-1]), "QAM grid")
+        if out is None:
+            out = self.empty(int(hi[-1]))
+        self._check_buf(out, int(hi[-1]), "high-rate output")
+        _check(lib().fc_tx_modulate(self._h, _ptr(grid), _ptr(out), _stream_handle(stream)), "fc_tx_modulate")
+        return out
+
     def rx_demod(self, y, out=None, stream=None):
         """Synchronised RX + OFDM demodulation: subcarrier values per symbol."""
         lo, hi = self.layout(OP_RXD)
@@ -281,7 +293,7 @@ class Plan:
         """Time the op's work splits on these buffers (out is overwritten) and
         keep the fastest; returns the choice and its time per call."""
         lo, hi = self.layout(op)
-        n_in, n_out = (int(lo[-1]), int(hi[-1])) if op == OP_TX else (int(hi[-1]), int(lo[-1]))
+        n_in, n_out = (int(lo[-1]), int(hi[-1])) if op in (OP_TX, OP_TXG) else (int(hi[-1]), int(lo[-1]))
         self._check_buf(inp, n_in, "input")
         self._check_buf(out, n_out, "output")
         r, c, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()

@@ -77,6 +77,18 @@ def oracle_tx(subbands, xs, Ds, reference="fc"):
     return streams
 
 
+def oracle_tx_grid(subbands, grids, Ds):
+    """Streams from QAM grids: CP-OFDM modulation with the truncated CP, then
+    the synchronised FC TX (oracle), summed per stream."""
+    off, lens, P = stream_offsets(subbands)
+    streams = [np.zeros(n, dtype=complex) for n in lens]
+    for i, s in enumerate(subbands):
+        p = P[i]
+        y = ofc.tx_sync_grid(grids[i], p["L"], p["N"], p["c"], Ds[i], p["ncp"])
+        streams[s["stream"]][off[i]:off[i] + len(y)] += y
+    return streams
+
+
 def oracle_rx(subbands, streams, Ds):
     off, lens, P = stream_offsets(subbands)
     outs = []

@@ -208,6 +208,22 @@ def test_rx_demod_tasks_hold_whole_symbols():
         assert p.stats(fc.OP_RXD)["tasks"] == -(-20 // k)
 
 
+def test_tx_grid_layout_and_validity():
+    """The grid-input TX reads n_symbols * n_active values per subband and
+    needs SYNC_OLA subbands; its blocks are the TX blocks."""
+    fc = _lib()
+    sbs, _ = W.mixed_numerology("sync_ola")
+    p = _plan(sbs)
+    lo, hi = p.layout(fc.OP_TXG)
+    assert list(np.diff(lo)) == [s["n_symbols"] * s["n_active"] for s in sbs]
+    assert list(hi) == list(p.layout(fc.OP_TX)[1])
+    assert p.stats(fc.OP_TXG) == p.stats(fc.OP_TX)
+    for mode in ("cont_ols", "sync_ols"):
+        s = W.subband(15, 2, 96, 8, 128, 1024, 0, mode)
+        with pytest.raises(fc.FcError):
+            _plan([s]).layout(fc.OP_TXG)
+
+
 def test_tuning_rejects_missing_op():
     fc = _lib()
     s = W.subband(15, 2, 96, 8, 128, 1024, 0, "sync_ols")

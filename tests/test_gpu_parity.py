@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from fc_cases import (GATE_DB, from_device, make_inputs, oracle_adj, oracle_rx, oracle_rxd, oracle_tx,
-                      stream_offsets, to_device)
+                      oracle_tx_grid, stream_offsets, to_device)
 from fcsynth import workloads as W
 from oracle import metrics
 
@@ -192,6 +192,49 @@ def test_rx_edge(name):
 def test_rx_demod_edge(name):
     got, ref = run_rx(EDGE[name], "c64", seed=23, weights="random", demod=True)
     assert_gate(got, ref, "c64", name)
+
+
+def run_tx_grid(subbands, io, seed=0, qam=16, weights="rc"):
+    import torch
+    from paper_2008_00672_amd import OP_TXG
+    _, Ds, grids = make_inputs(subbands, qam, seed, weights)
+    p = _plan(subbands, io, Ds)
+    lo, hi = p.layout(OP_TXG)
+    assert list(np.diff(lo)) == [g.size for g in grids]
+    y = p.tx_grid(to_device(_cat([g.ravel() for g in grids]), io))
+    torch.cuda.synchronize()
+    return _split(from_device(y, io), hi), oracle_tx_grid(subbands, grids, Ds)
+
+
+GRID = {
+    "sync_ola_frac": TINY_TX["sync_ola_frac"],
+    "sync_ola_64_256": TINY_TX["sync_ola_64_256"],
+    "two_sb_one_group": TINY_TX["two_sb_one_group"],
+    "one_symbol": EDGE["one_symbol_sync"],
+    "full_band": EDGE["full_band"],
+}
+
+
+@pytest.mark.parametrize("name", sorted(GRID))
+def test_tx_grid_tiny(name):
+    """QAM grid -> OFDM IFFT + truncated CP -> FC, in the kernels."""
+    got, ref = run_tx_grid(GRID[name], "c64", seed=29, weights="random")
+    assert_gate(got, ref, "c64", name)
+
+
+@pytest.mark.parametrize("io", ["c64", "f16"])
+def test_tx_grid_mixed_numerology(io):
+    sbs, meta = W.mixed_numerology("sync_ola")
+    got, ref = run_tx_grid(sbs, io, seed=meta["seed"], qam=meta["qam"])
+    assert_gate(got, ref, io, "mixed numerology grid TX")
+
+
+def test_tx_grid_shared_long_transform():
+    """Eight subbands on one stream and N: the full long IFFT path."""
+    sbs, _ = W.rx_filterbank(n_symbols=4)
+    sbs = [dict(s, mode="sync_ola") for s in sbs]
+    got, ref = run_tx_grid(sbs, "c64", seed=31, qam=256)
+    assert_gate(got, ref, "c64", "filterbank grid TX")
 
 
 def test_plain_slot_fp32():

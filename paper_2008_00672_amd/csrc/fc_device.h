@@ -549,18 +549,12 @@ template <int IO> struct LoadHigh : NoPrefetch {
 // RX short IFFT first pass from the subband's compacted region (bin u of the
 // subband at region[pad(u)], already in inverse-shift order), weighted by
 // D[p] and the conj phase; the transform then runs in place in the region.
-template <int NT, int L> struct LoadCompact {
+// (The weights are read when used: fetched ahead they would hold 16 registers
+// through the transform and push the RX kernel past four waves per SIMD.)
+template <int NT, int L> struct LoadCompact : NoPrefetch {
   const float2* R; const float* D; float2 ph;
-  float d[16];
-  __device__ __forceinline__ void prefetch(int tid) {
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      int u, b;
-      if (first_pos<NT, L, 0>(s, tid, u, b)) d[s] = D[(u + (L >> 1)) & (L - 1)];
-    }
-  }
-  __device__ __forceinline__ float2 operator()(int slot, int, int, int up) const {
-    return cscale(cmul(R[up], ph), d[slot]);
+  __device__ __forceinline__ float2 operator()(int, int u, int, int up) const {
+    return cscale(cmul(R[up], ph), D[(u + (L >> 1)) & (L - 1)]);
   }
 };
 

@@ -42,12 +42,14 @@ def stats_md(path, out, command):
     for r in rows:
         k = _short(r["Name"])
         avg = float(r["AverageNs"]) / 1e3
-        if k.startswith("fc_tx_"):
+        if OPS["fc_tx"](k):
             tx_avg += avg
         lines.append("| %s | %s | %.1f | %.2f | %.1f |" % (k, r["Calls"], avg, float(r["TotalDurationNs"]) / 1e6,
                                                           float(r["Percentage"])))
-    lines += ["", "Sum of the fc_tx_* class averages: %.1f us (the TX classes of one call run concurrently on "
-              "side streams, so this exceeds the call's wall time, which bench.py measures)." % tx_avg, ""]
+    lines += ["", "Sum of the TX class averages (template argument false: input is the low-rate signal): %.1f us. "
+              "The TX classes of one call run concurrently on side streams, so this exceeds the call's wall "
+              "time, which bench.py measures; the kernels with template argument true are the grid-input "
+              "TX (fc_tx_modulate), fc_rxd_kernel the demodulating RX, both timed outside the step." % tx_avg, ""]
     open(out, "w").write("\n".join(lines))
 
 
@@ -70,8 +72,17 @@ def _copy_reading(path, counter):
     return top[len(top) // 2]
 
 
+# kernels of one call of each operation
+OPS = {
+    "fc_tx": lambda k: k.startswith("fc_tx_") and k.endswith("false>"),       # TX from the low-rate signal
+    "fc_tx_grid": lambda k: k.startswith("fc_tx_") and k.endswith("true>"),   # TX from the QAM grid
+    "fc_rx": lambda k: k.startswith("fc_rx_kernel"),
+    "fc_rxd": lambda k: k.startswith("fc_rxd_kernel"),
+}
+
+
 def traffic(op, fetch, write, cfetch, cwrite, calls, out, command):
-    sel = (lambda k: k.startswith("fc_tx_")) if op == "fc_tx" else (lambda k: k.startswith("fc_rx_kernel"))
+    sel = OPS[op]
     f_kib, nf = _dispatch_values(fetch, "FETCH_SIZE", sel)
     w_kib, nw = _dispatch_values(write, "WRITE_SIZE", sel)
     ff = COPY_BYTES / (_copy_reading(cfetch, "FETCH_SIZE") * 1024.0)

@@ -214,6 +214,35 @@ def tx_sync(x, L, N, c, D, ncp):
     return y
 
 
+def tx_sync_ols(x, L, N, c, D, ncp):
+    """Symbol-synchronised OLS FC synthesis (Sec. III-D, the alternative to
+    the OLA scheme): the two blocks of each symbol are not windowed on the
+    input side; instead each filtered block is windowed after the
+    convolution so that only one block is non-zero in the overlap:
+    s_0 = [0_{N_L - N_CP,n}; 1_{N_S + N_CP,n}; 0_{N_T}] and
+    s_1 = [0_{N_L}; 1_{N_S}; 0_{N_T}] (no edge taper; the paper leaves the
+    taper shape open). The filtered symbols are then combined symbol-wise at
+    sigma_n as in the OLA scheme; their kept ranges tile the output."""
+    ov = Overlap(L, N, Fraction(1, 2))
+    lcp = lowrate_cp(ncp, ov.I, exact=False)
+    if any(lc > ov.L_L for lc in lcp):
+        raise ValueError("low-rate CP longer than the leading overlap L_L")
+    syms = split_symbols(x, L, lcp)
+    sig = sync_sigma(ncp, N)
+    out = np.zeros(sync_output_len(ncp, ov), dtype=complex)
+    T = block_core(L, N, c, D)
+    for n, xs in enumerate(syms):
+        zpad = np.r_[np.zeros(ov.L_L - lcp[n]), xs, np.zeros(ov.L_T)]
+        s_win = [np.r_[np.zeros(ov.N_L - ncp[n]), np.ones(ov.N_S + ncp[n]), np.zeros(ov.N_T)],
+                 np.r_[np.zeros(ov.N_L), np.ones(ov.N_S), np.zeros(ov.N_T)]]
+        th = unit_phase(c * sig[n], N)
+        for r in (0, 1):
+            blk = T @ zpad[r * L // 2:r * L // 2 + L]
+            ph_r = unit_phase(r * c * ov.L_S, L)
+            out[sig[n] + r * N // 2:sig[n] + r * N // 2 + N] += s_win[r] * np.sqrt(ov.I) * ph_r * th * blk
+    return out
+
+
 def perm_quarter(L, sign):
     """The selection matrices P_L^(+L/4) and P_L^(-L/4) of the RX
     concatenation (Sec. IV): they move the middle half [L/4, 3L/4) of a block

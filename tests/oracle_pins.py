@@ -236,6 +236,57 @@ def brute_sync(fc, L=8, N=32, c=-3, ncp=(6, 5, 5), seed=8):
     return rel(fc.tx_sync(x, L, N, c, D, list(ncp)), y)
 
 
+def pr1_sync_ols(fc, L=16, N=64, c=7, ncp=(8, 4, 4, 8, 4), seed=10):
+    """Synchronised OLS TX with unit weights on all L bins: every kept output
+    sample on the symbol's low-rate grid is the input sample (each block is
+    an ideal periodic interpolator; the kept windows tile the symbols)."""
+    rng = np.random.default_rng(seed)
+    I = N // L
+    ov = nu.Overlap(L, N)
+    lcp = nu.lowrate_cp(ncp, I, exact=True)
+    x = _cvec(rng, sum(L + l for l in lcp))
+    y = fc.tx_sync_ols(x, L, N, c, np.ones(L), list(ncp))
+    sig = nu.sync_sigma(ncp, N)
+    got = []
+    for n in range(len(ncp)):
+        t = sig[n] + I * (ov.L_L - lcp[n] + np.arange(L + lcp[n]))
+        got.append(y[t] * np.exp(-2j * np.pi * c * t / N) * np.sqrt(I))
+    return rel(np.concatenate(got), x)
+
+
+def brute_sync_ols(fc, L=8, N=32, c=5, ncp=(6, 5, 5), seed=11):
+    """Explicit loops of the time-domain circular convolution per block, the
+    output windows applied sample by sample."""
+    rng = np.random.default_rng(seed)
+    I = N // L
+    D = rng.uniform(-1.0, 1.0, L)
+    lcp = [v // I for v in ncp]
+    x = _cvec(rng, sum(L + v for v in lcp))
+    g0 = np.zeros(N, dtype=complex)
+    for d in range(N):
+        for p in range(L):
+            g0[d] += D[p] * np.exp(2j * np.pi * (p - L // 2) * d / N) / N
+    sig = [0]
+    for v in ncp[1:]:
+        sig.append(sig[-1] + N + v)
+    y = np.zeros(sig[-1] + 3 * N // 2, dtype=complex)
+    pos = 0
+    for n in range(len(ncp)):
+        z = np.zeros(3 * L // 2, dtype=complex)
+        z[L // 4 - lcp[n]:L // 4 - lcp[n] + L + lcp[n]] = x[pos:pos + L + lcp[n]]
+        pos += L + lcp[n]
+        for r in (0, 1):
+            s = z[r * L // 2:r * L // 2 + L]
+            lo = N // 4 - (ncp[n] if r == 0 else 0)
+            for tau in range(lo, 3 * N // 4):
+                acc = 0j
+                for i in range(L):
+                    acc += s[i] * g0[(tau - I * i) % N]
+                t = sig[n] + r * N // 2 + tau
+                y[t] += np.sqrt(I) * np.exp(2j * np.pi * c * t / N) * acc
+    return rel(fc.tx_sync_ols(x, L, N, c, D, list(ncp)), y)
+
+
 # -------------------------------------------------------------- adjoints --
 def adjoint_cont(fc, tx_ola, L=16, N=64, c=6, n=70, seed=9, lam=Fraction(1, 2)):
     rng = np.random.default_rng(seed)
@@ -375,5 +426,7 @@ ALL_PINS = {
     "reduced_vs_direct": lambda fc: reduced_vs_direct(fc),
     "ofdm_round_trip": lambda fc: ofdm_round_trip(fc),
     "ofdm_vs_numpy_fft": lambda fc: ofdm_vs_numpy_fft(fc),
+    "pr1_sync_ols": lambda fc: pr1_sync_ols(fc),
+    "brute_sync_ols": lambda fc: brute_sync_ols(fc),
 }
 TOL = 1e-10

@@ -51,6 +51,10 @@ MUTATIONS = {
     "reduced_block_swap": ("for g0, g1 in g:", "for g1, g0 in g:"),
     "blocks_freq_no_phase": ("g.append(phi_r * th_n * (Gf @ wn[r * N // 2:r * N // 2 + N]) / np.sqrt(ov.I))",
                              "g.append(th_n * (Gf @ wn[r * N // 2:r * N // 2 + N]) / np.sqrt(ov.I))"),
+    "ols_first_window_no_cp": ("np.r_[np.zeros(ov.N_L - ncp[n]), np.ones(ov.N_S + ncp[n]), np.zeros(ov.N_T)]",
+                               "np.r_[np.zeros(ov.N_L), np.ones(ov.N_S), np.zeros(ov.N_T)]"),
+    "ols_block_offset": ("blk = T @ zpad[r * L // 2:r * L // 2 + L]", "blk = T @ zpad[r * L // 4:r * L // 4 + L]"),
+    "ols_phase_dropped": ("ph_r = unit_phase(r * c * ov.L_S, L)", "ph_r = 1.0"),
     "ofdm_no_scale": ("x = np.sqrt(L) * (Winv @ X)", "x = Winv @ X"),
     "ofdm_forward": ("x = np.sqrt(L) * (Winv @ X)", "x = (dft_matrix(L) @ X) / np.sqrt(L)"),
     "ofdm_cp_from_start": ("out.append(np.r_[x[L - lcp[n]:], x])\n    return np.concatenate(out)\n\n\ndef tx_sync_grid",

@@ -69,7 +69,7 @@ enum {
   FC_OP_RX = 1,      /* fc_rx_analyze:    high-rate in, low-rate out                    */
   FC_OP_ADJ = 2,     /* fc_tx_adjoint:    high-rate in, low-rate CP-OFDM-shaped out     */
   FC_OP_RXD = 3,     /* fc_rx_demodulate: high-rate in, subcarriers out (synchronised)   */
-  FC_OP_TXG = 4      /* fc_tx_modulate:   QAM grid in, high-rate out (synchronised OLA)  */
+  FC_OP_TXG = 4      /* fc_tx_modulate:   QAM grid in, high-rate out (synchronised)      */
 };
 
 /*
@@ -181,8 +181,10 @@ fc_status fc_get_weights(const fc_plan* plan, int32_t sb, float* w_host, int32_t
  * FC synthesis filter bank (Sec. III-B, eq. for x_FC-F-OFDM; Sec. III-C..III-E):
  * lowrate_in (device, FC_OP_TX layout) -> highrate_out (device, all streams).
  * Every sample of every stream is written (zeros where no block contributes);
- * subbands on one stream are summed. Supported modes: FC_CONT_OLA,
- * FC_CONT_OLS, FC_SYNC_OLA.
+ * subbands on one stream are summed. All four modes; FC_SYNC_OLS is the
+ * synchronised scheme's OLS alternative (Sec. III-D: no input windows, each
+ * filtered block kept on s_0 = [0; 1_{N_S + N_CP,n}; 0] from the CP start or
+ * s_1 = [0_{N_L}; 1_{N_S}; 0_{N_T}], no edge taper).
  */
 fc_status fc_tx_synthesize(fc_plan* plan, const void* lowrate_in, void* highrate_out, void* stream);
 
@@ -204,8 +206,8 @@ fc_status fc_rx_analyze(fc_plan* plan, const void* highrate_in, void* lowrate_ou
  *                 n_active values (subcarriers kappa = -K/2 .. K/2-1), the
  *                 plan's I/O type; x_n = sqrt(L) W_L^{-1} X_n.
  *   highrate_out  device, high-rate layout, as fc_tx_synthesize.
- * Every subband must be FC_SYNC_OLA, else FC_E_STATE. Asynchronous on
- * `stream`; errors as fc_tx_synthesize.
+ * Every subband must be synchronised (FC_SYNC_OLA or FC_SYNC_OLS), else
+ * FC_E_STATE. Asynchronous on `stream`; errors as fc_tx_synthesize.
  */
 fc_status fc_tx_modulate(fc_plan* plan, const void* grid_in, void* highrate_out, void* stream);
 

@@ -237,12 +237,11 @@ void build_op(fc_plan* P, int kind) {
   Op& op = P->op[kind];
   op = Op();
   const int nsb = (int)P->subs.size();
-  // validity: TX needs CONT_* or SYNC_OLA; ADJ likewise; RX any; the
-  // demodulating RX needs synchronised subbands; the grid-input TX SYNC_OLA
+  // validity: TX any mode; ADJ CONT_* or SYNC_OLA; RX any; the
+  // demodulating RX and the grid-input TX synchronised subbands
   for (const Sub& s : P->subs) {
-    if ((kind == 0 || kind == 2) && s.d.mode == FC_SYNC_OLS) return;
-    if (kind == 3 && !s.sync) return;
-    if (kind == 4 && s.d.mode != FC_SYNC_OLA) return;
+    if (kind == 2 && s.d.mode == FC_SYNC_OLS) return;
+    if ((kind == 3 || kind == 4) && !s.sync) return;
   }
   op.valid = true;
   const int tk = kind == 4 ? 0 : kind;         // the grid-input TX is scheduled as the TX
@@ -386,7 +385,11 @@ void build_op(fc_plan* P, int kind) {
       // high-rate window
       if (tk == 0) {
         if (!G.sync && !G.ola) { bd.hlo = (int)s0.NL; bd.hhi = (int)(s0.NL + s0.NS); }
-        else { bd.hlo = 0; bd.hhi = N; }
+        else if (G.sync && !G.ola) {
+          // synchronised OLS: the synthesis windows s_0 (from the CP start) and s_1
+          bd.hlo = r == 0 ? (int)(s0.NL - s0.ncp[n]) : (int)s0.NL;
+          bd.hhi = (int)(s0.NL + s0.NS);
+        } else { bd.hlo = 0; bd.hhi = N; }
       } else {
         // RX of CONT_OLA (G^(OLA)) and ADJ of CONT_OLS window the high-rate input
         const bool win = !G.sync && ((kind == 1 && G.ola) || (kind == 2 && !G.ola));
@@ -413,7 +416,10 @@ void build_op(fc_plan* P, int kind) {
             w = Win{(int64_t)n * L, 0, L};
           } else {
             const int64_t xrel = s.pos[n] + (int64_t)r * (L / 2) - S_L;
-            w = (r == 0) ? Win{xrel, S_L, 3 * L / 4} : Win{xrel, L / 4, 3 * L / 4};
+            if (G.ola)       // OLA analysis windows a_0, a_1
+              w = (r == 0) ? Win{xrel, S_L, 3 * L / 4} : Win{xrel, L / 4, 3 * L / 4};
+            else             // OLS: the whole block of z = [0_{S_L}; x_CP; 0_{L_T}]
+              w = (r == 0) ? Win{xrel, S_L, L} : Win{xrel, 0, 3 * L / 4};
           }
         } else {
           phase_num = (int64_t)r * s.d.center_bin * s.LS * s.I;   // r c L_S / L in units of 1/N
@@ -446,7 +452,7 @@ void build_op(fc_plan* P, int kind) {
       const bool acc = P->groups.size() > 1 &&
           std::count_if(P->groups.begin(), P->groups.end(), [&](const Group& o) { return o.stream == G.stream; }) > 1;
       any_acc_tx |= acc;
-      const bool ola = G.sync || G.ola;
+      const bool ola = G.ola;
       int64_t total_blocks = 0;
       for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
       int K = P->run_len[0] > 0 ? P->run_len[0]

@@ -64,7 +64,9 @@ def oracle_tx(subbands, xs, Ds, reference="fc"):
     for i, s in enumerate(subbands):
         p = P[i]
         if reference == "fc":
-            if p["sync"]:
+            if p["sync"] and not p["ola"]:
+                y = ofc.tx_sync_ols(xs[i], p["L"], p["N"], p["c"], Ds[i], p["ncp"])
+            elif p["sync"]:
                 y = ofc.tx_sync(xs[i], p["L"], p["N"], p["c"], Ds[i], p["ncp"])
             else:
                 y = ofc.tx_cont(xs[i], p["L"], p["N"], p["c"], Ds[i], lam=p["lam"], ola=p["ola"])
@@ -84,7 +86,11 @@ def oracle_tx_grid(subbands, grids, Ds):
     streams = [np.zeros(n, dtype=complex) for n in lens]
     for i, s in enumerate(subbands):
         p = P[i]
-        y = ofc.tx_sync_grid(grids[i], p["L"], p["N"], p["c"], Ds[i], p["ncp"])
+        x = ofc.ofdm_modulate(grids[i], p["L"], p["lcp"])
+        if p["ola"]:
+            y = ofc.tx_sync(x, p["L"], p["N"], p["c"], Ds[i], p["ncp"])
+        else:
+            y = ofc.tx_sync_ols(x, p["L"], p["N"], p["c"], Ds[i], p["ncp"])
         streams[s["stream"]][off[i]:off[i] + len(y)] += y
     return streams
 

@@ -156,12 +156,18 @@ def test_compute_on_host_plan_is_state_error():
     assert st == -6
 
 
-def test_sync_ols_has_no_tx():
+def test_sync_ols_tx_and_no_adjoint():
+    """Synchronised OLS has a TX (output windows after the convolution, same
+    blocks and layout as synchronised OLA) but no adjoint."""
     fc = _lib()
     s = dict(W.rx_filterbank(14)[0][0])
     p = _plan([s])
+    q = _plan([dict(s, mode="sync_ola")])
+    assert list(p.layout(fc.OP_TX)[0]) == list(q.layout(fc.OP_TX)[0])
+    assert list(p.layout(fc.OP_TX)[1]) == list(q.layout(fc.OP_TX)[1])
+    assert p.stats(fc.OP_TX)["blocks"] == q.stats(fc.OP_TX)["blocks"]
     with pytest.raises(fc.FcError):
-        p.layout(fc.OP_TX)
+        p.layout(fc.OP_ADJ)
     p.layout(fc.OP_RX)
 
 
@@ -210,7 +216,7 @@ def test_rx_demod_tasks_hold_whole_symbols():
 
 def test_tx_grid_layout_and_validity():
     """The grid-input TX reads n_symbols * n_active values per subband and
-    needs SYNC_OLA subbands; its blocks are the TX blocks."""
+    needs synchronised subbands; its blocks are the TX blocks."""
     fc = _lib()
     sbs, _ = W.mixed_numerology("sync_ola")
     p = _plan(sbs)
@@ -218,17 +224,16 @@ def test_tx_grid_layout_and_validity():
     assert list(np.diff(lo)) == [s["n_symbols"] * s["n_active"] for s in sbs]
     assert list(hi) == list(p.layout(fc.OP_TX)[1])
     assert p.stats(fc.OP_TXG) == p.stats(fc.OP_TX)
-    for mode in ("cont_ols", "sync_ols"):
-        s = W.subband(15, 2, 96, 8, 128, 1024, 0, mode)
-        with pytest.raises(fc.FcError):
-            _plan([s]).layout(fc.OP_TXG)
+    s = W.subband(15, 2, 96, 8, 128, 1024, 0, "cont_ols")
+    with pytest.raises(fc.FcError):
+        _plan([s]).layout(fc.OP_TXG)
 
 
 def test_tuning_rejects_missing_op():
     fc = _lib()
     s = W.subband(15, 2, 96, 8, 128, 1024, 0, "sync_ols")
     with pytest.raises(fc.FcError):
-        _plan([s]).set_tuning(fc.OP_TX, 8, 1)
+        _plan([s]).set_tuning(fc.OP_ADJ, 8, 1)
 
 
 def test_graph_calls_reject_bad_arguments():

@@ -43,7 +43,11 @@ def assert_grad(got, ref, what, bins=None):
         assert e <= GRAD_GATE_DB, "%s subband %d: %.1f dB" % (what, k, e)
 
 
-@pytest.mark.parametrize("name", sorted(TINY_TX))
+# (synchronised OLS has no adjoint operator, hence no gradient entry points)
+GRAD_CASES = sorted(k for k, v in TINY_TX.items() if all(s["mode"] != "sync_ols" for s in v))
+
+
+@pytest.mark.parametrize("name", GRAD_CASES)
 def test_weight_grad_tiny(name):
     sbs = TINY_TX[name]
     xs, Ds, _ = make_inputs(sbs, 16, 21, "random")

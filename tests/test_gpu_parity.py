@@ -92,6 +92,10 @@ TINY_TX = {
     "i1_cont_ols": [tiny("cont_ols", L=32, N=32, c=0, ncp=[4, 3, 3, 3, 4], K=16, n_tb=2)],
     "two_sb_one_group": [tiny("sync_ola", L=16, N=128, c=-20, ncp=CP_FRAC[:3] + [9, 9], n_sym=5),
                          tiny("sync_ola", L=32, N=128, c=25, ncp=CP_FRAC[:3] + [9, 9], n_sym=5, K=16, n_tb=4)],
+    "sync_ols_frac": [tiny("sync_ols", ncp=CP_FRAC)],
+    "sync_ols_64_256": [tiny("sync_ols", L=64, N=256, c=-40, ncp=[20, 18, 18, 18, 20], K=40, n_tb=8)],
+    "sync_ols_two_sb": [tiny("sync_ols", L=16, N=128, c=-20, ncp=CP_FRAC[:3] + [9, 9], n_sym=5),
+                        tiny("sync_ols", L=32, N=128, c=25, ncp=CP_FRAC[:3] + [9, 9], n_sym=5, K=16, n_tb=4)],
 }
 
 
@@ -208,6 +212,7 @@ def run_tx_grid(subbands, io, seed=0, qam=16, weights="rc"):
 
 GRID = {
     "sync_ola_frac": TINY_TX["sync_ola_frac"],
+    "sync_ols_64_256": TINY_TX["sync_ols_64_256"],
     "sync_ola_64_256": TINY_TX["sync_ola_64_256"],
     "two_sb_one_group": TINY_TX["two_sb_one_group"],
     "one_symbol": EDGE["one_symbol_sync"],
@@ -249,6 +254,14 @@ def test_mixed_numerology_tx(io):
     sbs, meta = W.mixed_numerology("sync_ola")
     got, ref = run_tx(sbs, io, seed=meta["seed"], qam=meta["qam"])
     assert_gate(got, ref, io, "mixed numerology TX")
+
+
+def test_mixed_numerology_tx_sync_ols():
+    """Synchronised OLS TX of the two-numerology subframe (accumulating groups
+    on one stream)."""
+    sbs, meta = W.mixed_numerology("sync_ols")
+    got, ref = run_tx(sbs, "c64", seed=meta["seed"], qam=meta["qam"])
+    assert_gate(got, ref, "c64", "mixed numerology sync OLS TX")
 
 
 def test_mixed_numerology_rx():

@@ -8,7 +8,11 @@
  *     (Sec. III-B, block operators F^(OLA), F^(OLS); Sec. IV, G^(OLA), G^(OLS));
  *   - symbol-synchronised FC whose blocks align with every OFDM symbol and its
  *     NR cyclic prefix, with CP truncation/extrapolation (Sec. III-C..III-E)
- *     and the synchronised receiver with CP removal (Sec. IV).
+ *     and the synchronised receiver with CP removal (Sec. IV);
+ *   - the synchronised receiver with OFDM demodulation in the simplified
+ *     joint form (Sec. V-A), the transmitter from QAM grids with the OFDM
+ *     modulation in the kernels, the adjoint and the weight gradient, HIP
+ *     graph capture and an autotuner for the work split.
  *
  * Conventions (all arguments are plain C types; no framework types cross this
  * boundary):
@@ -23,7 +27,10 @@
  *     device tables (descriptors, twiddles, weights).
  *   - Calls that take a stream are asynchronous on that stream (a hipStream_t
  *     passed as void*; NULL means the default stream) and never synchronise the
- *     host. A plan must not be used on two streams concurrently.
+ *     host, except where a function says so (weights from host memory,
+ *     tuning, autotuning). A plan must not be used on two streams
+ *     concurrently or from two host threads at once; different plans are
+ *     independent.
  *   - Every function returns an fc_status and never aborts or throws across
  *     the ABI. Argument and shape errors are detected on the host before any
  *     device work is queued. HIP runtime failures surface as FC_E_DEVICE.
@@ -53,7 +60,7 @@ enum {
   FC_CONT_OLA = 0,   /* continuous, fixed overlap, overlap-add                 */
   FC_CONT_OLS = 1,   /* continuous, fixed overlap, overlap-save                */
   FC_SYNC_OLA = 2,   /* symbol-synchronised: OLA transmitter, CP-removing receiver */
-  FC_SYNC_OLS = 3    /* symbol-synchronised receiver only                      */
+  FC_SYNC_OLS = 3    /* symbol-synchronised: OLS transmitter (output windows), same receiver */
 };
 
 /* Storage type of the interleaved I/Q samples in device memory. */
@@ -275,8 +282,10 @@ fc_status fc_plan_stats(const fc_plan* plan, int32_t op, int64_t* n_blocks, int6
  *            stream plus side streams owned by the plan.
  * Results do not depend on the tuning (same arithmetic per block).
  * fc_plan_set_tuning waits for the plan's device to go idle and rebuilds the
- * op's work tables. Errors: FC_E_ARG (out of range), FC_E_STATE (op not
- * available for this plan), FC_E_NOMEM / FC_E_DEVICE.
+ * op's work tables (freeing the old ones): graphs captured before hold the
+ * old tables' addresses and must be captured again. Errors: FC_E_ARG (out
+ * of range), FC_E_STATE (op not available for this plan), FC_E_NOMEM /
+ * FC_E_DEVICE.
  */
 fc_status fc_plan_set_tuning(fc_plan* plan, int32_t op, int32_t run_len, int32_t conc);
 fc_status fc_plan_get_tuning(const fc_plan* plan, int32_t op, int32_t* run_len, int32_t* conc);
@@ -301,9 +310,11 @@ fc_status fc_plan_autotune(fc_plan* plan, int32_t op, const void* in, void* out,
  * is recorded (kernel launches, fills, fork/join of the side streams; none
  * allocates or synchronises), and fc_graph_end instantiates the graph.
  * fc_graph_launch replays it on any stream. Plans and buffers are recorded
- * by address and must outlive the graph; weights changed later with
- * fc_set_weights* are used by later replays. Errors: FC_E_ARG, FC_E_DEVICE
- * (capture or instantiation failed, e.g. a non-capturable call in between).
+ * by address and must outlive the graph, and so must the plans' work tables:
+ * fc_plan_set_tuning and fc_plan_autotune rebuild them, so capture after
+ * tuning. Weights changed later with fc_set_weights* are used by later
+ * replays. Errors: FC_E_ARG, FC_E_DEVICE (capture or instantiation failed,
+ * e.g. a non-capturable call in between).
  */
 typedef struct fc_graph fc_graph;
 fc_status fc_graph_begin(void* stream);

@@ -391,6 +391,18 @@ template <int IO, int NT, int P> struct LoadAhead : NoPrefetch {
     // precedes them they would only lengthen register live ranges
     asm volatile("" : "+v"(tid) : : "memory");
     valid = 0;
+    if (lo <= 0 && hi >= P) {
+      // the whole block is valid (a uniform branch): no per-sample checks
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        int i, b;
+        if (first_pos<NT, P, 0>(s, tid, i, b)) {
+          raw[s] = x[i];
+          valid |= 1u << s;
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       int i, b;
@@ -528,10 +540,12 @@ struct StoreScatter : NoPrefetch {
   float2* S; const uint64_t* map;
   __device__ __forceinline__ void operator()(int, int t, float2 v, int) const {
     const uint64_t e = map[t];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t d = (uint32_t)(e >> (16 * k)) & 0xffffu;
-      if (d != 0xffffu) S[d] = v;
+    const uint32_t e01 = (uint32_t)e, e23 = (uint32_t)(e >> 32);
+    if ((e01 & 0xffffu) != 0xffffu) S[e01 & 0xffffu] = v;
+    if ((e01 >> 16) != 0xffffu) S[e01 >> 16] = v;
+    if (e23 != 0xffffffffu) {          // third and fourth destinations are rare
+      if ((e23 & 0xffffu) != 0xffffu) S[e23 & 0xffffu] = v;
+      if ((e23 >> 16) != 0xffffu) S[e23 >> 16] = v;
     }
   }
 };

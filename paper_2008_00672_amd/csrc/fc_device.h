@@ -134,15 +134,22 @@ __device__ __forceinline__ void group_sync() {
   if constexpr (NT == kThreads) __syncthreads(); else wave_sync();
 }
 
-template <int R> struct TwB {
-  float4 v[R >= 8 ? 2 : 1];
+// Twiddle bases of one butterfly: (w, w^2), and (w^4, w^8) for radix >= 8.
+struct TwB {
+  float4 v[2];
 };
 
-template <int NT, int P, int LOGBT, int S, int MAXIT, int R>
-__device__ __forceinline__ void twb_load(TwB<R> (&t)[MAXIT], const float2* __restrict__ twb, int tid) {
-  constexpr int NS = ns_of(P, S);
+template <int P, int R, int LOGBT, int NT>
+constexpr int maxit() { return (((P / R) << LOGBT) + NT - 1) / NT; }
+
+template <int NT, int P, int LOGBT, int S, int RM, int MM>
+__device__ __forceinline__ void twb_load(TwB (&t)[MM], const float2* __restrict__ twb, int tid) {
+  constexpr int R = radix_of(P, S, RM);
+  constexpr int NS = ns_of(P, S, RM);
   constexpr int TOTAL = (P / R) << LOGBT;
-  const float4* base = reinterpret_cast<const float4*>(twb + twb_off(P, S));
+  constexpr int MAXIT = maxit<P, R, LOGBT, NT>();
+  constexpr int OFF = twb_off(P, S, RM);      // folded here, not evaluated per call
+  const float4* base = reinterpret_cast<const float4*>(twb + OFF);
 #pragma unroll
   for (int it = 0; it < MAXIT; ++it) {
     const int g = tid + it * NT;
@@ -159,7 +166,7 @@ __device__ __forceinline__ float2 twc(float a, float b) { return make_float2(a, 
 
 // v[r] *= w^r for r = 1..R-1 (w^r from the four bases; DIR > 0 conjugates).
 template <int R, int DIR>
-__device__ __forceinline__ void apply_twiddles(float2* v, const TwB<R>& t) {
+__device__ __forceinline__ void apply_twiddles(float2* v, const TwB& t) {
   const float2 w1 = twc<DIR>(t.v[0].x, t.v[0].y);
   if constexpr (R == 2) {
     v[1] = cmul(v[1], w1);
@@ -192,9 +199,9 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const TwB<R>& t) {
 }
 
 // Slot s of the first pass: element index i and transform b it loads.
-template <int NT, int P, int LOGBT>
+template <int NT, int P, int LOGBT, int RM = 16>
 __device__ __forceinline__ bool first_pos(int s, int tid, int& i, int& b) {
-  constexpr int R = radix_of(P, 0);
+  constexpr int R = radix_of(P, 0, RM);
   constexpr int NB = P / R;
   constexpr int TOTAL = NB << LOGBT;
   const int it = s / R, r = s % R;
@@ -206,9 +213,9 @@ __device__ __forceinline__ bool first_pos(int s, int tid, int& i, int& b) {
 }
 
 // Output position of register slot s of the last pass (-1: slot unused).
-template <int NT, int P, int LOGBT>
+template <int NT, int P, int LOGBT, int RM = 16>
 __device__ __forceinline__ int last_pos(int s, int tid) {
-  constexpr int R = radix_of(P, npass(P) - 1);
+  constexpr int R = radix_of(P, npass(P, RM) - 1, RM);
   constexpr int NB = P / R;
   constexpr int TOTAL = NB << LOGBT;
   const int it = s / R, r = s % R;
@@ -218,9 +225,6 @@ __device__ __forceinline__ int last_pos(int s, int tid) {
   return ((j + r * NB) << LOGBT) + b;
 }
 
-template <int P, int R, int LOGBT, int NT>
-constexpr int maxit() { return (((P / R) << LOGBT) + NT - 1) / NT; }
-
 // One Stockham pass over P-point transforms, 2^LOGBT of them interleaved
 // (element i of transform b at index i * 2^LOGBT + b), run by NT threads.
 // NS is the product of the radices of the previous passes. The first pass
@@ -228,7 +232,7 @@ constexpr int maxit() { return (((P / R) << LOGBT) + NT - 1) / NT; }
 // store(slot, t, v, tp); ip / tp are the padded LDS positions of the element.
 template <int NT, int P, int LOGBT, int R, int NS, int DIR, bool FIRST, bool LAST, class Load, class Store>
 __device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load& load, Store& store,
-                                         const TwB<R>* tb) {
+                                         const TwB* tb) {
   constexpr int NB = P / R;
   constexpr int BT = 1 << LOGBT;
   constexpr int TOTAL = NB * BT;
@@ -280,16 +284,45 @@ __device__ __forceinline__ void fft_pass(float2* __restrict__ buf, int tid, Load
   if constexpr (!LAST) group_sync<NT>();
 }
 
+// Largest number of per-thread transform slots over the non-first passes.
+template <int NT, int P, int LOGBT, int RM>
+constexpr int max_maxit() {
+  int m = 1;
+  for (int s = 1; s < npass(P, RM); ++s) {
+    const int R = radix_of(P, s, RM);
+    const int v = (((P / R) << LOGBT) + NT - 1) / NT;
+    if (v > m) m = v;
+  }
+  return m;
+}
+
+template <int NT, int P, int LOGBT, int RM, int S, int MM>
+__device__ __forceinline__ void twb_load_from(TwB (*t)[MM], const float2* __restrict__ twb, int tid) {
+  if constexpr (S < npass(P, RM)) {
+    twb_load<NT, P, LOGBT, S, RM, MM>(t[S - 1], twb, tid);
+    twb_load_from<NT, P, LOGBT, RM, S + 1, MM>(t, twb, tid);
+  }
+}
+
+template <int NT, int P, int LOGBT, int DIR, int RM, int S, int MM, class Load, class Store>
+__device__ __forceinline__ void passes_from(float2* buf, int tid, Load& load, Store& store, TwB (*t)[MM]) {
+  constexpr int NP = npass(P, RM);
+  fft_pass<NT, P, LOGBT, radix_of(P, S, RM), ns_of(P, S, RM), DIR, S == 0, S == NP - 1>(
+      buf, tid, load, store, t[S == 0 ? 0 : S - 1]);
+  if constexpr (S + 1 < NP) passes_from<NT, P, LOGBT, DIR, RM, S + 1, MM>(buf, tid, load, store, t);
+}
+
 // Whole transform: DIR = -1 forward DFT, +1 unnormalised inverse, of 2^LOGBT
-// interleaved P-point transforms. The caller provides a barrier before the
-// call when `buf`, or what `load` reads, was written by other threads.
-// load.prefetch / store.prefetch are called first, so functors can start
-// their own global loads (weights, twiddles) before the passes run.
-template <int NT, int P, int LOGBT, int DIR, class Load, class Store>
+// interleaved P-point transforms with the radix plan RM (see radix_of). The
+// caller provides a barrier before the call when `buf`, or what `load`
+// reads, was written by other threads. load.prefetch / store.prefetch are
+// called first, so functors can start their own global loads (weights,
+// twiddles) before the passes run; every pass's twiddle bases are fetched
+// then as well.
+template <int NT, int P, int LOGBT, int DIR, int RM = 16, class Load, class Store>
 __device__ __forceinline__ void fft_run(float2* buf, int tid, Load& load, Store& store,
                                         const float2* __restrict__ twb) {
-  constexpr int NP = npass(P);
-  constexpr int R0 = radix_of(P, 0), R1 = radix_of(P, 1), R2 = radix_of(P, 2);
+  constexpr int NP = npass(P, RM);
   static_assert(NT == kThreads || P <= 1024, "one wave holds at most 1024 points");
   // All LDS and twiddle indices of a pass depend only on the thread, so the
   // compiler would compute every transform's indices (and twiddle loads) once
@@ -298,16 +331,12 @@ __device__ __forceinline__ void fft_run(float2* buf, int tid, Load& load, Store&
   // thread index and the table pointer are made opaque per transform.
   asm volatile("" : "+v"(tid));
   asm volatile("" : "+s"(twb));
-  constexpr int M1 = maxit<P, R1, LOGBT, NT>(), M2 = maxit<P, R2, LOGBT, NT>();
-  TwB<R1> t1[M1];
-  TwB<R2> t2[M2];
-  if constexpr (NP >= 2) twb_load<NT, P, LOGBT, 1>(t1, twb, tid);
-  if constexpr (NP >= 3) twb_load<NT, P, LOGBT, 2>(t2, twb, tid);
+  constexpr int MM = max_maxit<NT, P, LOGBT, RM>();
+  TwB t[NP > 1 ? NP - 1 : 1][MM];
+  twb_load_from<NT, P, LOGBT, RM, 1, MM>(t, twb, tid);
   load.prefetch(tid);
   store.prefetch(tid);
-  fft_pass<NT, P, LOGBT, R0, 1, DIR, true, NP == 1>(buf, tid, load, store, (const TwB<R0>*)nullptr);
-  if constexpr (NP >= 2) fft_pass<NT, P, LOGBT, R1, R0, DIR, false, NP == 2>(buf, tid, load, store, t1);
-  if constexpr (NP >= 3) fft_pass<NT, P, LOGBT, R2, R0 * R1, DIR, false, true>(buf, tid, load, store, t2);
+  passes_from<NT, P, LOGBT, DIR, RM, 0, MM>(buf, tid, load, store, t);
 }
 
 template <int V> struct SizeC { static constexpr int value = V; };
@@ -490,7 +519,7 @@ template <int NT, int L> struct StoreBand {
 // of residue rho takes V[rho] * exp(+j 2 pi q b / N), q the band bin of rho.
 // The twiddles depend only on the thread and the subband, so they are fetched
 // before the short FFT of the block runs.
-template <int NT, int L, int LOGI> struct LoadPruned {
+template <int NT, int L, int LOGI, int RM> struct LoadPruned {
   static constexpr int N = L << LOGI;
   const float2* V; const float2* tw; int q0;
   float2 w[16];
@@ -498,7 +527,7 @@ template <int NT, int L, int LOGI> struct LoadPruned {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       int rho, b;
-      if (first_pos<NT, L, LOGI>(s, tid, rho, b)) {
+      if (first_pos<NT, L, LOGI, RM>(s, tid, rho, b)) {
         const int q = (q0 + ((rho - q0) & (L - 1))) & (N - 1);
         w[s] = tw[((q * b) & (N - 1)) * (kTwiddleN / N)];
       }
@@ -603,12 +632,12 @@ __device__ __forceinline__ TxWin tx_window(const BlockDesc& B, const TaskDesc& T
 }
 
 // Epilogue phase 2 (after a barrier): OLA carry-out or write the owned samples.
-template <int IO, int NT, int P, int LOGBT>
+template <int IO, int NT, int P, int LOGBT, int RM = 16>
 __device__ __forceinline__ void tx_epilogue(const TxEpi& ep, float2* pend, const TxWin& w,
                                             typename Io<IO>::T* ob, bool acc, int tid) {
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    const int t = last_pos<NT, P, LOGBT>(s, tid);
+    const int t = last_pos<NT, P, LOGBT, RM>(s, tid);
     if (t < 0) continue;
     if (t >= w.cth) pend[t - w.cth] = ep.val[s];
     else if (t >= w.wlo && t < w.whi) put<IO>(ob, t, ep.val[s], acc);
@@ -672,7 +701,9 @@ __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void
     if constexpr (FRONT) ld.issue_grid(at<IO>(a.in, Z0.x0), Z0.K, sid);
     else ld.issue(at<IO>(a.in, Z0.x0), Z0.lo, Z0.hi, sid);
   }
-  LoadPruned<kThreads, L, LOGI> lp;
+  // radix plan of the long IFFT: every thread takes part in every pass
+  constexpr int RM = radix_cap(N);
+  LoadPruned<kThreads, L, LOGI, RM> lp;
   lp.tw = tw; lp.q0 = S.q0;
   if constexpr (kKeepTwiddles) lp.prefetch(rtid);
   for (int g0 = 0; g0 < T.blk_count; g0 += NB) {
@@ -713,13 +744,13 @@ __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void
       TxEpi ep;
       ep.pend = pend; ep.pth = w.pth;
       if constexpr (kKeepTwiddles) {
-        NoPrefetchWrap<LoadPruned<kThreads, L, LOGI>> lpw{lp};
-        fft_run<kThreads, L, LOGI, +1>(buf, rtid, lpw, ep, twb);
+        NoPrefetchWrap<LoadPruned<kThreads, L, LOGI, RM>> lpw{lp};
+        fft_run<kThreads, L, LOGI, +1, RM>(buf, rtid, lpw, ep, twb);
       } else {
-        fft_run<kThreads, L, LOGI, +1>(buf, rtid, lp, ep, twb);
+        fft_run<kThreads, L, LOGI, +1, RM>(buf, rtid, lp, ep, twb);
       }
       __syncthreads();
-      tx_epilogue<IO, kThreads, L, LOGI>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0, rtid);
+      tx_epilogue<IO, kThreads, L, LOGI, RM>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0, rtid);
       prev_end = T.ola ? B.t0 + N : INT64_MIN;
     }
   }

@@ -42,36 +42,63 @@ struct Cf {   // complex float with the same layout as HIP's float2
 };
 
 // ------------------------------------------------------------ pass plan ---
-constexpr int npass(int P) { return P <= 16 ? 1 : (P <= 256 ? 2 : 3); }
-constexpr int radix_of(int P, int s) {
-  // 2..16: one pass; 32..256: two; 512..4096: three
-  return P <= 16 ? P
-       : P == 32 ? (s == 0 ? 8 : 4)
-       : P == 64 ? 8
-       : P == 128 ? (s == 0 ? 16 : 8)
-       : P == 256 ? 16
-       : P == 512 ? 8
-       : P == 1024 ? (s < 2 ? 16 : 4)
-       : P == 2048 ? (s < 2 ? 16 : 8)
-       : 16;
+constexpr int ilog2c(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Radix plans of a P-point transform. RM = 16 (default): the hand-picked
+// plans below (2..16: one pass; 32..256: two; 512..4096: three). RM = 8 or 4:
+// passes of at most 3 or 2 bits, larger passes first, for transforms whose
+// radix-16 butterflies would leave threads idle (fewer points than 16 per
+// thread): more passes, every thread busy.
+constexpr int npass(int P, int RM = 16) {
+  return RM >= 16 ? (P <= 16 ? 1 : (P <= 256 ? 2 : 3)) : (ilog2c(P) + ilog2c(RM) - 1) / ilog2c(RM);
+}
+constexpr int radix_of(int P, int s, int RM = 16) {
+  return RM >= 16 ? (P <= 16 ? P
+                     : P == 32 ? (s == 0 ? 8 : 4)
+                     : P == 64 ? 8
+                     : P == 128 ? (s == 0 ? 16 : 8)
+                     : P == 256 ? 16
+                     : P == 512 ? 8
+                     : P == 1024 ? (s < 2 ? 16 : 4)
+                     : P == 2048 ? (s < 2 ? 16 : 8)
+                     : 16)
+                  : 1 << (ilog2c(P) / npass(P, RM) + (s < ilog2c(P) % npass(P, RM) ? 1 : 0));
 }
 
 // Per-pass twiddle bases. A non-first pass with NS preceding points and radix
 // R needs w^r = exp(DIR j 2 pi k r / (NS R)) for r = 1..R-1 at its butterfly
-// index k. The table holds, per (P, pass, k), the four bases w^1, w^2, w^4,
-// w^8 (32 bytes, FP64-computed on the host); the other powers are products of
-// at most three bases, so each butterfly loads two 16-byte vectors instead of
-// R-1 separate twiddles, and all passes' bases are fetched when a transform
-// starts, off the pass-to-pass critical path.
-constexpr int ns_of(int P, int s) { return s == 0 ? 1 : (s == 1 ? radix_of(P, 0) : radix_of(P, 0) * radix_of(P, 1)); }
-constexpr int twb_size(int P, int s) { return (s >= 1 && s < npass(P)) ? 4 * ns_of(P, s) : 0; }
-constexpr int twb_off(int P, int s) {
+// index k. The table holds, per (plan, P, pass, k), the four bases w^1, w^2,
+// w^4, w^8 (32 bytes, FP64-computed on the host); the other powers are
+// products of at most three bases, so each butterfly loads two 16-byte
+// vectors instead of R-1 separate twiddles, and all passes' bases are fetched
+// when a transform starts, off the pass-to-pass critical path. Layout: the
+// RM = 16 plans of all sizes, then the RM = 8 ones, then RM = 4.
+constexpr int ns_of(int P, int s, int RM = 16) {
+  int ns = 1;
+  for (int t = 0; t < s; ++t) ns *= radix_of(P, t, RM);
+  return ns;
+}
+constexpr int twb_size(int P, int s, int RM = 16) {
+  return (s >= 1 && s < npass(P, RM)) ? 4 * ns_of(P, s, RM) : 0;
+}
+constexpr int twb_plan_total(int RM, int upto = 2 * kMaxPoints) {
   int off = 0;
-  for (int q = 2; q < P; q <<= 1) off += twb_size(q, 1) + twb_size(q, 2);
-  for (int t = 1; t < s; ++t) off += twb_size(P, t);
+  for (int q = 2; q < upto; q <<= 1)
+    for (int t = 1; t < npass(q, RM); ++t) off += twb_size(q, t, RM);
   return off;
 }
-constexpr int twb_total() { return twb_off(2 * kMaxPoints, 1); }
+constexpr int twb_off(int P, int s, int RM = 16) {
+  int off = (RM < 16 ? twb_plan_total(16) : 0) + (RM < 8 ? twb_plan_total(8) : 0) + twb_plan_total(RM, P);
+  for (int t = 1; t < s; ++t) off += twb_size(P, t, RM);
+  return off;
+}
+constexpr int twb_total() { return twb_plan_total(16) + twb_plan_total(8) + twb_plan_total(4); }
+// largest radix for interleaved transforms of N points in all on 256 threads
+constexpr int radix_cap(int N) { return N >= 4096 ? 16 : (N >= 2048 ? 8 : 4); }
 
 // One subband, shared by all operations.
 struct SbDesc {

@@ -798,17 +798,19 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
     tw[k] = Cf{(float)std::cos(a), (float)-std::sin(a)};
   }
   // per-pass bases w^1, w^2, w^4, w^8 of w = exp(-j 2 pi k / (NS R)) for every
-  // non-first pass of every transform size (layout: twb_off)
+  // non-first pass of every transform size and radix plan (layout: twb_off)
   std::vector<Cf> twp(twb_total());
-  for (int Pn = 2; Pn <= kMaxPoints; Pn <<= 1) {
-    for (int sp = 1; sp < npass(Pn); ++sp) {
-      const int NS = ns_of(Pn, sp), R = radix_of(Pn, sp);
-      for (int k = 0; k < NS; ++k) {
-        const int e[4] = {1, 2, 4, 8};
-        for (int q = 0; q < 4; ++q) {
-          const int64_t num = imod((int64_t)k * e[q], (int64_t)NS * R);
-          const double a = 2.0 * kPi * (double)num / (double)(NS * R);
-          twp[twb_off(Pn, sp) + 4 * k + q] = Cf{(float)std::cos(a), (float)-std::sin(a)};
+  for (int RM : {16, 8, 4}) {
+    for (int Pn = 2; Pn <= kMaxPoints; Pn <<= 1) {
+      for (int sp = 1; sp < npass(Pn, RM); ++sp) {
+        const int NS = ns_of(Pn, sp, RM), R = radix_of(Pn, sp, RM);
+        for (int k = 0; k < NS; ++k) {
+          const int e[4] = {1, 2, 4, 8};
+          for (int q = 0; q < 4; ++q) {
+            const int64_t num = imod((int64_t)k * e[q], (int64_t)NS * R);
+            const double a = 2.0 * kPi * (double)num / (double)(NS * R);
+            twp[twb_off(Pn, sp, RM) + 4 * k + q] = Cf{(float)std::cos(a), (float)-std::sin(a)};
+          }
         }
       }
     }

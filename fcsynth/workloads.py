@@ -66,3 +66,11 @@ def rx_filterbank(n_symbols=280):
         sbs.append(subband(30, n_symbols, 12 * W, 8, L, 4096, s + 6 * W, 'sync_ols'))
         s += 12 * W
     return sbs, dict(qam=256, seed=4, io='bf16', snr_db=30.0)
+
+
+def wideband_slot(mode):
+    """10 MHz uplink at 15 kHz with a 1024-point high-rate transform: one
+    subband of 52 PRB (624 active subcarriers) centred at bin 0, an 8-bin
+    transition band on each side, L = N = 1024 (I = 1, the channel-filter
+    case), one 14-symbol slot of 64-QAM; mode 'cont_ols' or 'sync_ola'."""
+    return [subband(15, 14, 624, 8, 1024, 1024, 0, mode)], dict(qam=64, seed=6, io='c64')

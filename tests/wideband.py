@@ -1,0 +1,105 @@
+"""Method-level check on the wide-band allocation of the paper's numerical
+results (Sec. VI, wide-band case): continuous against symbol-synchronised
+processing of one 52-PRB subband at N = 1024, 15 kHz.
+
+Four chains (TX scheme x RX scheme), as in the paper's table of filtering
+configurations: continuous OLS TX or synchronised OLA TX, followed by
+continuous OLS RX (then CP removal and the OFDM FFT) or the synchronised RX
+with OFDM demodulation. Reported per chain: the EVM of the active
+subcarriers against the transmitted 64-QAM symbols (FFT window after the
+full CP, the window the synchronised receiver uses); per TX scheme: the
+out-of-band power ratio of the Welch PSD. No noise is added, so the EVM is
+the filtering's own distortion.
+
+The two TX layouts differ only by where the first CP starts; the signals are
+moved between them by that offset (``to_sync`` / ``to_cont``).
+
+Test infrastructure: the oracle side calls ``oracle`` only; the GPU side
+calls the library only and takes its inputs from the same seeded generators.
+"""
+import numpy as np
+
+from fc_cases import make_inputs, sub_params
+from fcsynth import workloads as W
+from oracle import fc as ofc
+from oracle import metrics
+from oracle import numerology as nu
+
+OOB_GUARD = 8          # bins excluded on each side of the transition bands
+
+
+class Setup:
+    def __init__(self):
+        self.sb = {m: W.wideband_slot(m)[0][0] for m in ("cont_ols", "sync_ola")}
+        self.meta = W.wideband_slot("cont_ols")[1]
+        self.pc, self.ps = sub_params(self.sb["cont_ols"]), sub_params(self.sb["sync_ola"])
+        xs, Ds, grids = make_inputs([self.sb["cont_ols"]], self.meta["qam"], self.meta["seed"])
+        self.x, self.D, self.grid = xs[0], Ds[0], grids[0]
+        s = self.sb["cont_ols"]
+        self.L, self.N, self.K, self.n_tb = s["n_short"], s["n_long"], s["n_active"], s["n_tb"]
+        self.act = metrics.active_bins(self.L, self.K)
+        self.d = (nu.first_cp_start(False, self.pc["ov"], self.pc["ncp"][0])
+                  - nu.first_cp_start(True, self.ps["ov"], self.ps["ncp"][0]))
+
+    def to_sync(self, y):
+        out = np.zeros(self.ps["Q"], dtype=complex)
+        seg = y[self.d:self.d + self.ps["Q"]]
+        out[:len(seg)] = seg
+        return out
+
+    def to_cont(self, y):
+        out = np.zeros(self.pc["Q"], dtype=complex)
+        n = min(len(y), self.pc["Q"] - self.d)
+        out[self.d:self.d + n] = y[:n]
+        return out
+
+    def evm_lowrate(self, xh):
+        """Continuous RX output (low-rate CP-OFDM stream) -> EVM of the
+        active subcarriers, window after the full CP."""
+        syms = ofc.split_symbols(xh, self.L, self.pc["lcp"])
+        sc = metrics.ofdm_demod(np.stack([s[len(s) - self.L:] for s in syms]))
+        return metrics.err_db(sc[:, self.act], self.grid)
+
+    def evm_subcarriers(self, sc):
+        return metrics.err_db(np.asarray(sc).reshape(-1, self.L)[:, self.act], self.grid)
+
+    def oob(self, y):
+        return metrics.oob_ratio_db(y, self.N, [(0, self.K, self.n_tb)], guard=OOB_GUARD)
+
+
+def oracle_chains(S):
+    """FP64 oracle: TX outputs and the report of the four chains."""
+    L, N, D = S.L, S.N, S.D
+    y = {"cont": ofc.tx_cont(S.x, L, N, 0, D, ola=False),
+         "sync": ofc.tx_sync(S.x, L, N, 0, D, S.ps["ncp"])}
+    rx_cont = lambda yh: S.evm_lowrate(ofc.rx_cont(yh, L, N, 0, D, S.pc["n_in"], ola=False))
+    rx_sync = lambda yh: S.evm_subcarriers(ofc.rx_sync_subcarriers(yh, L, N, 0, D, S.ps["ncp"]))
+    evm = {"cont_tx/cont_rx": rx_cont(y["cont"]), "cont_tx/sync_rx": rx_sync(S.to_sync(y["cont"])),
+           "sync_tx/cont_rx": rx_cont(S.to_cont(y["sync"])), "sync_tx/sync_rx": rx_sync(y["sync"])}
+    oob = {k: S.oob(v) for k, v in y.items()}
+    return y, dict(evm_db=evm, oob_db=oob)
+
+
+def gpu_chains(S):
+    """The same chains through the library (FP32 I/O)."""
+    import torch
+    from fc_cases import from_device, to_device
+    from paper_2008_00672_amd import Plan
+    plans = {}
+    for k, m in (("cont", "cont_ols"), ("sync", "sync_ola")):
+        p = Plan([S.sb[m]], io="c64", device=0)
+        p.set_weights(0, S.D)
+        plans[k] = p
+    y = {k: from_device(p.tx(to_device(S.x, "c64")), "c64") for k, p in plans.items()}
+
+    def rx_cont(yh):
+        return S.evm_lowrate(from_device(plans["cont"].rx(to_device(yh, "c64")), "c64"))
+
+    def rx_sync(yh):
+        return S.evm_subcarriers(from_device(plans["sync"].rx_demod(to_device(yh, "c64")), "c64"))
+
+    evm = {"cont_tx/cont_rx": rx_cont(y["cont"]), "cont_tx/sync_rx": rx_sync(S.to_sync(y["cont"])),
+           "sync_tx/cont_rx": rx_cont(S.to_cont(y["sync"])), "sync_tx/sync_rx": rx_sync(y["sync"])}
+    torch.cuda.synchronize()
+    oob = {k: S.oob(v) for k, v in y.items()}
+    return y, dict(evm_db=evm, oob_db=oob)

@@ -176,6 +176,12 @@ EDGE = {
     "edge_center_pos": [tiny("sync_ola", L=64, N=256, c=96, K=40, n_tb=8, ncp=[20, 18, 18, 18, 20])],
     "edge_center_neg": [tiny("sync_ola", L=64, N=256, c=-96, K=40, n_tb=8, ncp=[20, 18, 18, 18, 20])],
     "i1_2048": [W.subband(15, 1, 1200, 8, 2048, 2048, 0, "cont_ols")],
+    # largest transforms: the whole 4096-bin band as one subband (I = 1), and
+    # the narrowest subband at the largest interpolation (L = 16, I = 256)
+    "max_4096": [W.subband(30, 1, 3276, 8, 4096, 4096, 0, "sync_ola")],
+    "narrow_4096": [W.subband(15, 2, 12, 2, 16, 4096, -1500, "sync_ola")],
+    # no active subcarriers: only the transition bins carry weight
+    "no_active": [tiny("sync_ola", K=0, n_tb=4, ncp=[9, 5, 6, 7, 5])],
 }
 
 

@@ -321,7 +321,7 @@ def single_unit_latency(ptx1, prx1, x_dev, r_dev, gs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+        print("bench.py: the benchmark runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         return 2
     import torch

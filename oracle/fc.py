@@ -5,7 +5,7 @@ Test infrastructure only (see ``oracle/__init__``). No FFTs: every DFT is a
 dense matrix with integer-reduced exponents, W_n[k, l] = exp(-j2pi((k*l) mod n)/n),
 and W_n^{-1} = conj(W_n)/n (Sec. III-B).
 
-Conventions fixed by this oracle (readings of the paper):
+Conventions fixed by this oracle (readings of the paper where it is silent):
  * bins are 0-based: Xi(p) = (c - ceil(L/2) + p) mod N; c may be negative;
  * the weights D are real and indexed in fftshifted order (p = kappa + L/2);
  * TX scale sqrt(I) (Sec. III-B, first equation of the continuous SFB);

@@ -214,27 +214,49 @@ def tx_sync(x, L, N, c, D, ncp):
     return y
 
 
-def tx_sync_ols(x, L, N, c, D, ncp):
+def taper_ramp(T):
+    """Rising edge of T samples, w_i = sin^2(pi (i + 1/2) / (2T)), i = 0..T-1.
+    Sec. III-D asks for a smooth edge without giving its shape; this raised
+    cosine is symmetric about its midpoint, so the falling edge w_{T-1-i}
+    equals 1 - w_i and the two edges of neighbouring symbols cross-fade."""
+    i = np.arange(T)
+    return np.sin(np.pi * (i + 0.5) / (2 * T)) ** 2
+
+
+def tx_sync_ols(x, L, N, c, D, ncp, taper=0):
     """Symbol-synchronised OLS FC synthesis (Sec. III-D, the alternative to
     the OLA scheme): the two blocks of each symbol are not windowed on the
     input side; instead each filtered block is windowed after the
     convolution so that only one block is non-zero in the overlap:
     s_0 = [0_{N_L - N_CP,n}; 1_{N_S + N_CP,n}; 0_{N_T}] and
-    s_1 = [0_{N_L}; 1_{N_S}; 0_{N_T}] (no edge taper; the paper leaves the
-    taper shape open). The filtered symbols are then combined symbol-wise at
-    sigma_n as in the OLA scheme; their kept ranges tile the output."""
+    s_1 = [0_{N_L}; 1_{N_S}; 0_{N_T}]. The filtered symbols are then combined
+    symbol-wise at sigma_n as in the OLA scheme; their kept ranges tile the
+    output.
+
+    taper = T > 0 (even) smooths the symbol's outer edges, the rising edge of
+    s_0 and the falling edge of s_1 (Sec. III-D): each becomes the ramp of
+    ``taper_ramp`` over the T samples centred on the hard edge, so the
+    falling edge of one symbol and the rising edge of the next overlap and
+    add. Needs T/2 <= N_L - N_CP,n and T/2 <= N_T."""
     ov = Overlap(L, N, Fraction(1, 2))
     lcp = lowrate_cp(ncp, ov.I, exact=False)
     if any(lc > ov.L_L for lc in lcp):
         raise ValueError("low-rate CP longer than the leading overlap L_L")
+    if taper % 2 or taper < 0 or taper // 2 > ov.N_T or any(taper // 2 > ov.N_L - v for v in ncp):
+        raise ValueError("taper must be even and fit the leading and trailing overlaps")
     syms = split_symbols(x, L, lcp)
     sig = sync_sigma(ncp, N)
     out = np.zeros(sync_output_len(ncp, ov), dtype=complex)
     T = block_core(L, N, c, D)
+    ramp, h = taper_ramp(taper), taper // 2
     for n, xs in enumerate(syms):
         zpad = np.r_[np.zeros(ov.L_L - lcp[n]), xs, np.zeros(ov.L_T)]
         s_win = [np.r_[np.zeros(ov.N_L - ncp[n]), np.ones(ov.N_S + ncp[n]), np.zeros(ov.N_T)],
                  np.r_[np.zeros(ov.N_L), np.ones(ov.N_S), np.zeros(ov.N_T)]]
+        if taper:
+            e0, e1 = ov.N_L - ncp[n], ov.N_L + ov.N_S      # the hard edges being smoothed
+            s_win[0][e0 - h:e0 + h] = ramp
+            s_win[1][e1 - h:e1 + h] = ramp[::-1]
         th = unit_phase(c * sig[n], N)
         for r in (0, 1):
             blk = T @ zpad[r * L // 2:r * L // 2 + L]

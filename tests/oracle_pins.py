@@ -254,10 +254,15 @@ def pr1_sync_ols(fc, L=16, N=64, c=7, ncp=(8, 4, 4, 8, 4), seed=10):
     return rel(np.concatenate(got), x)
 
 
-def brute_sync_ols(fc, L=8, N=32, c=5, ncp=(6, 5, 5), seed=11):
+def brute_sync_ols(fc, L=8, N=32, c=5, ncp=(6, 5, 5), seed=11, taper=0):
     """Explicit loops of the time-domain circular convolution per block, the
-    output windows applied sample by sample."""
+    output windows applied sample by sample. With a taper of T samples the
+    first block's output before its kept range and the second block's after
+    it are kept too, T/2 samples each side of the edge, weighted by the
+    cross-fade weight w(k) = sin^2(pi (k + 1/2) / (2T)) (k counted along the
+    edge in time), its mirror 1 - w(k) on the falling edge."""
     rng = np.random.default_rng(seed)
+    h = taper // 2
     I = N // L
     D = rng.uniform(-1.0, 1.0, L)
     lcp = [v // I for v in ncp]
@@ -278,13 +283,40 @@ def brute_sync_ols(fc, L=8, N=32, c=5, ncp=(6, 5, 5), seed=11):
         for r in (0, 1):
             s = z[r * L // 2:r * L // 2 + L]
             lo = N // 4 - (ncp[n] if r == 0 else 0)
-            for tau in range(lo, 3 * N // 4):
+            start, stop = (lo - h, 3 * N // 4) if r == 0 else (lo, 3 * N // 4 + h)
+            for tau in range(start, stop):
                 acc = 0j
                 for i in range(L):
                     acc += s[i] * g0[(tau - I * i) % N]
+                wgt = 1.0
+                if r == 0 and tau < lo + h:
+                    wgt = np.sin(np.pi * (tau - (lo - h) + 0.5) / (2 * taper)) ** 2
+                if r == 1 and tau >= 3 * N // 4 - h:
+                    wgt = 1.0 - np.sin(np.pi * (tau - (3 * N // 4 - h) + 0.5) / (2 * taper)) ** 2
                 t = sig[n] + r * N // 2 + tau
-                y[t] += np.sqrt(I) * np.exp(2j * np.pi * c * t / N) * acc
-    return rel(fc.tx_sync_ols(x, L, N, c, D, list(ncp)), y)
+                y[t] += wgt * np.sqrt(I) * np.exp(2j * np.pi * c * t / N) * acc
+    return rel(fc.tx_sync_ols(x, L, N, c, D, list(ncp), taper=taper) if taper else
+               fc.tx_sync_ols(x, L, N, c, D, list(ncp)), y)
+
+
+def taper_interior(fc, L=16, N=64, c=-5, ncp=(9, 5, 6, 7), T=6, seed=12):
+    """Tapering changes nothing outside the T-sample edges around the symbol
+    boundaries, and the falling and rising edges of neighbouring symbols
+    cross-fade to one (rising + mirrored rising = 1)."""
+    rng = np.random.default_rng(seed)
+    I = N // L
+    D = rng.uniform(-1.0, 1.0, L)
+    lcp = nu.lowrate_cp(list(ncp), I, exact=False)
+    x = _cvec(rng, sum(L + v for v in lcp))
+    y0 = fc.tx_sync_ols(x, L, N, c, D, list(ncp))
+    y1 = fc.tx_sync_ols(x, L, N, c, D, list(ncp), taper=T)
+    sig = nu.sync_sigma(list(ncp), N)
+    edge = np.zeros(len(y0), dtype=bool)
+    for n in range(len(ncp)):
+        for e in (sig[n] + N // 4 - ncp[n], sig[n] + N // 2 + 3 * N // 4):
+            edge[e - T // 2:e + T // 2] = True
+    w = fc.taper_ramp(T)
+    return rel(y1[~edge], y0[~edge]) + float(np.max(np.abs(w + w[::-1] - 1.0)))
 
 
 # -------------------------------------------------------------- adjoints --
@@ -428,5 +460,7 @@ ALL_PINS = {
     "ofdm_vs_numpy_fft": lambda fc: ofdm_vs_numpy_fft(fc),
     "pr1_sync_ols": lambda fc: pr1_sync_ols(fc),
     "brute_sync_ols": lambda fc: brute_sync_ols(fc),
+    "brute_sync_ols_taper": lambda fc: brute_sync_ols(fc, taper=4),
+    "taper_interior": lambda fc: taper_interior(fc),
 }
 TOL = 1e-10

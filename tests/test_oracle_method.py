@@ -121,3 +121,23 @@ def test_blocks_per_two_symbols():
     n_in = 2 * L + sum(c * L // N for c in ncp)
     assert nu.cont_block_count(n_in, nu.Overlap(L, N, Fraction(1, 2))) == 5
     assert 2 * len(ncp) == 4
+
+
+def test_sync_ols_taper_leakage():
+    """Sec. III-D: the hard edges of the synchronised OLS output windows leak
+    out of band, smooth edges reduce the leakage, and the OLA scheme is the
+    better TX choice in general."""
+    import fcsynth
+    from oracle import weights as ow
+    rng = np.random.default_rng(5)
+    L, N, K, n_tb, c = 64, 256, 40, 8, -30
+    ncp = nu.nr_cp_list(N, 0, 0, 14)
+    lcp = nu.lowrate_cp(ncp, N // L, exact=False)
+    x = fcsynth.cp_ofdm(fcsynth.qam_grid(rng, 64, 14, K), L, lcp)
+    D = ow.rc_weights(L, K, n_tb)
+    oob = lambda y: metrics.oob_ratio_db(y, N, [(c, K, n_tb)], guard=8)
+    ols = [oob(ofc.tx_sync_ols(x, L, N, c, D, ncp, taper=T)) for T in (0, 8, 16, 32)]
+    ola = oob(ofc.tx_sync(x, L, N, c, D, ncp))
+    print("OOB dB: OLS taper 0/8/16/32", ["%.1f" % v for v in ols], "OLA %.1f" % ola, flush=True)
+    assert all(a > b for a, b in zip(ols, ols[1:]))
+    assert ola < ols[0]

@@ -62,6 +62,9 @@ MUTATIONS = {
     "ofdm_subcarrier_shift": ("X[np.arange(-K // 2, K // 2) % L] = grid[n]\n        x = np.sqrt(L)",
                               "X[np.arange(-K // 2 + 1, K // 2 + 1) % L] = grid[n]\n        x = np.sqrt(L)"),
     "blocks_freq_theta_sign": ("th_n = np.conj(unit_phase(c * sigma[n], N))", "th_n = unit_phase(c * sigma[n], N)"),
+    "taper_falling_not_mirrored": ("s_win[1][e1 - h:e1 + h] = ramp[::-1]", "s_win[1][e1 - h:e1 + h] = ramp"),
+    "taper_edge_off_by_one": ("s_win[0][e0 - h:e0 + h] = ramp", "s_win[0][e0 - h + 1:e0 + h + 1] = ramp"),
+    "taper_shape_offset": ("return np.sin(np.pi * (i + 0.5) / (2 * T)) ** 2", "return np.sin(np.pi * (i + 1) / (2 * T)) ** 2"),
 }
 
 

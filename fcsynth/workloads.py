@@ -2,17 +2,18 @@
 
 Each subband is a dict with the fields of the C-ABI subband descriptor:
 scs_khz, first_symbol, n_symbols, n_active (K), n_tb, n_short (L), n_long (N),
-center_bin (c), overlap (num, den), mode, stream. Modes are the strings
+center_bin (c), overlap (num, den), mode, stream, taper. Modes are the strings
 'cont_ola', 'cont_ols', 'sync_ola', 'sync_ols'.
 """
 import numpy as np
 
 
 def subband(scs_khz, n_symbols, n_active, n_tb, n_short, n_long, center_bin, mode,
-            stream=0, first_symbol=0, overlap=(1, 2)):
+            stream=0, first_symbol=0, overlap=(1, 2), taper=0):
     return dict(scs_khz=scs_khz, first_symbol=first_symbol, n_symbols=n_symbols,
                 n_active=n_active, n_tb=n_tb, n_short=n_short, n_long=n_long,
-                center_bin=center_bin, overlap=tuple(overlap), mode=mode, stream=stream)
+                center_bin=center_bin, overlap=tuple(overlap), mode=mode, stream=stream,
+                taper=taper)
 
 
 def next_pow2(v):

@@ -98,6 +98,14 @@ enum {
  *   ncp_high      optional per-symbol high-rate CP lengths N_CP,n (n_symbols
  *                 entries, read during fc_plan_create only); NULL selects the
  *                 NR normal CP at rate n_long * SCS
+ *   taper         FC_SYNC_OLS only (0 otherwise): length T (even, high-rate
+ *                 samples) of the smooth outer edges of the TX output windows
+ *                 (Sec. III-D): the rising edge of s_0 and the falling edge of
+ *                 s_1 become raised-cosine ramps w_i = sin^2(pi (i + 1/2)/(2T))
+ *                 over the T samples centred on the hard edge, so the edges of
+ *                 neighbouring symbols cross-fade; T/2 <= N_L - N_CP,n for every
+ *                 symbol and T/2 <= N_T; 0 keeps the hard edges. The receiver
+ *                 does not depend on it.
  */
 typedef struct fc_subband {
   int32_t scs_khz;
@@ -113,6 +121,7 @@ typedef struct fc_subband {
   int32_t mode;
   int32_t stream;
   const int32_t* ncp_high;
+  int32_t taper;
 } fc_subband;
 
 typedef struct fc_plan fc_plan;
@@ -191,7 +200,8 @@ fc_status fc_get_weights(const fc_plan* plan, int32_t sb, float* w_host, int32_t
  * subbands on one stream are summed. All four modes; FC_SYNC_OLS is the
  * synchronised scheme's OLS alternative (Sec. III-D: no input windows, each
  * filtered block kept on s_0 = [0; 1_{N_S + N_CP,n}; 0] from the CP start or
- * s_1 = [0_{N_L}; 1_{N_S}; 0_{N_T}], no edge taper).
+ * s_1 = [0_{N_L}; 1_{N_S}; 0_{N_T}]; hard edges, or smooth outer edges of the
+ * subband's taper length, see fc_subband).
  */
 fc_status fc_tx_synthesize(fc_plan* plan, const void* lowrate_in, void* highrate_out, void* stream);
 

@@ -559,6 +559,30 @@ struct TxEpi : NoPrefetch {
   }
 };
 
+// Same, with the output window of a tapered synchronised OLS block applied
+// before the carry-in (taper = 0: no window). The window is zero outside
+// [lo, hi), one inside, with a rising edge w_i = sin^2(pi (i + 1/2) / (2T))
+// over [lo, lo + T) and/or the mirrored falling edge over [hi - T, hi).
+struct TxEpiWin : TxEpi {
+  int lo, hi, taper; bool rise, fall;
+  __device__ __forceinline__ void set_window(int32_t win, int T) {
+    lo = win & 8191; hi = (win >> 13) & 8191; rise = (win >> 26) & 1; fall = (win >> 27) & 1; taper = T;
+  }
+  __device__ __forceinline__ float ramp(int i) const {
+    const float s = sinf(3.14159265358979f * (float)(2 * i + 1) / (float)(4 * taper));
+    return s * s;
+  }
+  __device__ __forceinline__ void operator()(int slot, int t, float2 v, int tp) {
+    if (taper) {
+      float w = (t >= lo && t < hi) ? 1.f : 0.f;
+      if (rise && t >= lo && t < lo + taper) w = ramp(t - lo);
+      if (fall && t >= hi - taper && t < hi) w = ramp(hi - 1 - t);
+      v = cscale(v, w);
+    }
+    TxEpi::operator()(slot, t, v, tp);
+  }
+};
+
 // RX, last pass of the long FFT: each bin q goes straight to every subband
 // region that gathers it (up to four LDS destinations per bin, 16 bits each,
 // 0xffff = none; built by the planner). The regions overlay the spectrum: all
@@ -817,8 +841,9 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
     __syncthreads();
     LoadLds ls;
     ls.s = S;
-    TxEpi ep;
+    TxEpiWin ep;
     ep.pend = pend; ep.pth = w.pth;
+    ep.set_window(B.win, G.taper);
     fft_run<kThreads, NL, 0, +1>(S, tid, ls, ep, tw);
     __syncthreads();
     tx_epilogue<IO, kThreads, NL, 0>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0, (int)threadIdx.x);

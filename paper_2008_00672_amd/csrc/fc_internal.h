@@ -124,7 +124,7 @@ struct GroupDesc {
   int32_t wstride;           // weight gradient: scratch entries per wave (one-wave transforms)
   int32_t acc_off;           // weight gradient: LDS offset (complex entries) of the accumulators
   int32_t acc_len;           // weight gradient: accumulator floats (sum of the subbands' L)
-  int32_t pad1;
+  int32_t taper;             // TX, synchronised OLS: edge length T of the output windows (0: hard edges)
 };
 
 // One FC block of a group.
@@ -132,8 +132,15 @@ struct BlockDesc {
   int64_t t0;                // absolute high-rate element index of block sample 0
   int32_t hlo, hhi;          // TX: high-rate write window; RX: high-rate input window
   int32_t bs;                // index of the block's first BlockSb entry
-  int32_t pad0;
+  int32_t win;               // TX with taper: output window, see win_pack
 };
+
+// Output window of a tapered synchronised OLS TX block: support [lo, hi) of
+// the block, a rising edge of T samples starting at lo and/or a falling edge
+// of T samples ending at hi (T = GroupDesc::taper). lo, hi <= 4096.
+constexpr int32_t win_pack(int lo, int hi, bool rise, bool fall) {
+  return lo | (hi << 13) | ((rise ? 1 : 0) << 26) | ((fall ? 1 : 0) << 27);
+}
 
 // Per (block, subband).
 struct BlockSb {

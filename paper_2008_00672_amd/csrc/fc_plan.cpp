@@ -67,6 +67,7 @@ struct Group {
   std::vector<int> subs;       // plan subband indices
   int N;
   bool sync, ola;
+  int taper;                   // synchronised OLS TX: output-window edge length
   int64_t offset;              // within the stream
   int64_t Q;
   int rank;                    // order of the group within its stream
@@ -206,6 +207,12 @@ fc_status analyse(const fc_subband& d, Sub& s) {
     s.Q = (R - 1) * s.NS + s.N;
     s.first_cp = s.NO;
   }
+  // smooth output-window edges (synchronised OLS TX): each ramp lies inside
+  // the block, next to its kept range
+  if (d.taper < 0 || (d.taper & 1) || (d.taper && d.mode != FC_SYNC_OLS)) return FC_E_ARG;
+  if (d.taper / 2 > s.NT) return FC_E_SHAPE;
+  for (int n = 0; n < d.n_symbols; ++n)
+    if (d.taper / 2 > s.NL - s.ncp[n]) return FC_E_SHAPE;
   s.w = rc_default(s.L, d.n_active, d.n_tb);
   return FC_OK;
 }
@@ -291,7 +298,9 @@ void build_op(fc_plan* P, int kind) {
     gd.N = G.N; gd.logN = ilog2(G.N);
     gd.n_sb = (int)OG.subs.size(); gd.sb_first = (int)op.sb.size();
     const Sub& s0 = P->subs[OG.subs[0]];
-    gd.prune = (tk == 0 && OG.subs.size() == 1 && s0.I >= 2 && s0.L >= 16) ? 1 : 0;
+    // tapered output windows are applied by the full-transform kernel only
+    gd.taper = tk == 0 ? G.taper : 0;
+    gd.prune = (tk == 0 && OG.subs.size() == 1 && s0.I >= 2 && s0.L >= 16 && !gd.taper) ? 1 : 0;
     op.grp.push_back(gd);
     int cofs = 0;
     for (int m : OG.subs) {
@@ -385,7 +394,15 @@ void build_op(fc_plan* P, int kind) {
       // high-rate window
       if (tk == 0) {
         if (!G.sync && !G.ola) { bd.hlo = (int)s0.NL; bd.hhi = (int)(s0.NL + s0.NS); }
-        else if (G.sync && !G.ola) {
+        else if (G.sync && !G.ola && G.taper) {
+          // synchronised OLS with smooth outer edges: the windows overlap at
+          // symbol boundaries, so the blocks are combined by OLA; the window
+          // itself is applied in the kernel
+          const int h = G.taper / 2;
+          bd.hlo = 0; bd.hhi = N;
+          bd.win = r == 0 ? win_pack((int)(s0.NL - s0.ncp[n]) - h, (int)(s0.NL + s0.NS), true, false)
+                          : win_pack((int)s0.NL, (int)(s0.NL + s0.NS) + h, false, true);
+        } else if (G.sync && !G.ola) {
           // synchronised OLS: the synthesis windows s_0 (from the CP start) and s_1
           bd.hlo = r == 0 ? (int)(s0.NL - s0.ncp[n]) : (int)s0.NL;
           bd.hhi = (int)(s0.NL + s0.NS);
@@ -452,7 +469,7 @@ void build_op(fc_plan* P, int kind) {
       const bool acc = P->groups.size() > 1 &&
           std::count_if(P->groups.begin(), P->groups.end(), [&](const Group& o) { return o.stream == G.stream; }) > 1;
       any_acc_tx |= acc;
-      const bool ola = G.ola;
+      const bool ola = G.ola || G.taper > 0;
       int64_t total_blocks = 0;
       for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
       int K = P->run_len[0] > 0 ? P->run_len[0]
@@ -742,15 +759,15 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   for (int m = 0; m < n_sb; ++m) used[sb[m].stream] = 1;
   for (int u : used) if (!u) { delete P; return FC_E_ARG; }
   // processing groups: same stream, long transform, model and CP schedule
-  std::map<std::tuple<int, int, int, int, int, std::vector<int>>, int> key2g;
+  std::map<std::tuple<int, int, int, int, int, std::vector<int>, int>, int> key2g;
   for (int m = 0; m < n_sb; ++m) {
     Sub& s = P->subs[m];
     auto key = std::make_tuple(s.d.stream, s.N, s.d.mode, s.d.overlap_num * 4096 / s.d.overlap_den,
-                               s.d.n_symbols, s.ncp);
+                               s.d.n_symbols, s.ncp, s.d.taper);
     auto it = key2g.find(key);
     if (it == key2g.end()) {
       Group g{};
-      g.stream = s.d.stream; g.N = s.N; g.sync = s.sync; g.ola = s.ola;
+      g.stream = s.d.stream; g.N = s.N; g.sync = s.sync; g.ola = s.ola; g.taper = s.d.taper;
       g.Q = s.Q;
       g.R = s.sync ? 2 * s.d.n_symbols : (int)((s.n_in + s.LT + s.LS - 1) / s.LS);
       key2g[key] = (int)P->groups.size();

@@ -30,7 +30,7 @@ class FcSubband(ctypes.Structure):
     _fields_ = [("scs_khz", _I32), ("first_symbol", _I32), ("n_symbols", _I32), ("n_active", _I32),
                 ("n_tb", _I32), ("n_short", _I32), ("n_long", _I32), ("center_bin", _I32),
                 ("overlap_num", _I32), ("overlap_den", _I32), ("mode", _I32), ("stream", _I32),
-                ("ncp_high", _I32P)]
+                ("ncp_high", _I32P), ("taper", _I32)]
 
 
 EXPORTS = {
@@ -121,7 +121,7 @@ class Plan:
             arr[i] = FcSubband(s["scs_khz"], s.get("first_symbol", 0), s["n_symbols"], s["n_active"],
                                s["n_tb"], s["n_short"], s["n_long"], s["center_bin"], num, den,
                                MODES[s["mode"]] if isinstance(s["mode"], str) else s["mode"],
-                               s.get("stream", 0), cp_ptr)
+                               s.get("stream", 0), cp_ptr, s.get("taper", 0))
         h = ctypes.c_void_p()
         _check(lib().fc_plan_create(arr, len(subbands), IOS[io], device, ctypes.byref(h)), "fc_plan_create")
         self._h = h

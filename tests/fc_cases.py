@@ -65,7 +65,7 @@ def oracle_tx(subbands, xs, Ds, reference="fc"):
         p = P[i]
         if reference == "fc":
             if p["sync"] and not p["ola"]:
-                y = ofc.tx_sync_ols(xs[i], p["L"], p["N"], p["c"], Ds[i], p["ncp"])
+                y = ofc.tx_sync_ols(xs[i], p["L"], p["N"], p["c"], Ds[i], p["ncp"], taper=s.get("taper", 0))
             elif p["sync"]:
                 y = ofc.tx_sync(xs[i], p["L"], p["N"], p["c"], Ds[i], p["ncp"])
             else:
@@ -90,7 +90,7 @@ def oracle_tx_grid(subbands, grids, Ds):
         if p["ola"]:
             y = ofc.tx_sync(x, p["L"], p["N"], p["c"], Ds[i], p["ncp"])
         else:
-            y = ofc.tx_sync_ols(x, p["L"], p["N"], p["c"], Ds[i], p["ncp"])
+            y = ofc.tx_sync_ols(x, p["L"], p["N"], p["c"], Ds[i], p["ncp"], taper=s.get("taper", 0))
         streams[s["stream"]][off[i]:off[i] + len(y)] += y
     return streams
 

@@ -122,6 +122,10 @@ BAD = {
     "cont_fractional_cp": (dict(mode="cont_ols", n_short=64, n_active=40, n_tb=8), "FC_E_SHAPE"),
     "sync_cp_too_long": (dict(mode="sync_ola", ncp_high=[600] * 14), "FC_E_SHAPE"),
     "zero_symbols": (dict(n_symbols=0), "FC_E_ARG"),
+    "taper_not_sync_ols": (dict(taper=16), "FC_E_ARG"),
+    "taper_odd": (dict(mode="sync_ols", taper=15), "FC_E_ARG"),
+    "taper_negative": (dict(mode="sync_ols", taper=-2), "FC_E_ARG"),
+    "taper_past_leading_overlap": (dict(mode="sync_ols", taper=706), "FC_E_SHAPE"),
 }
 CODES = {"FC_E_ARG": -1, "FC_E_SHAPE": -2, "FC_E_UNSUPPORTED": -3}
 
@@ -243,3 +247,17 @@ def test_graph_calls_reject_bad_arguments():
     assert L.fc_graph_end(None, None) == -1
     assert L.fc_graph_launch(None, None) == -1
     L.fc_graph_destroy(None)
+
+
+def test_sync_ols_taper_plan():
+    """A taper changes neither the layout nor the receiver; the longest taper
+    the CP schedule allows (T/2 = N_L - max N_CP,n = 512 - 160) is accepted."""
+    fc = _lib()
+    s = dict(W.plain_tx_slot()[0][0], mode="sync_ols")
+    p0 = fc.Plan([s], device=-1)
+    p1 = fc.Plan([dict(s, taper=704)], device=-1)
+    for op in (fc.OP_TX, fc.OP_RX, fc.OP_RXD, fc.OP_TXG):
+        assert [list(a) for a in p0.layout(op)] == [list(a) for a in p1.layout(op)]
+    assert p1.stats(fc.OP_TX)["blocks"] == p0.stats(fc.OP_TX)["blocks"]
+    assert p1.stats(fc.OP_RX) == p0.stats(fc.OP_RX)
+

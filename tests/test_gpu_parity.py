@@ -74,8 +74,8 @@ def assert_gate(got, ref, io, extra=""):
         assert e <= GATE_DB[io], "part %d: %.1f dB" % (k, e)
 
 
-def tiny(mode, L=16, N=64, c=5, n_sym=5, lam=(1, 2), ncp=None, K=8, n_tb=2):
-    s = W.subband(15, n_sym, K, n_tb, L, N, c, mode, overlap=lam)
+def tiny(mode, L=16, N=64, c=5, n_sym=5, lam=(1, 2), ncp=None, K=8, n_tb=2, taper=0):
+    s = W.subband(15, n_sym, K, n_tb, L, N, c, mode, overlap=lam, taper=taper)
     s["ncp_high"] = ncp
     return s
 
@@ -96,6 +96,14 @@ TINY_TX = {
     "sync_ols_64_256": [tiny("sync_ols", L=64, N=256, c=-40, ncp=[20, 18, 18, 18, 20], K=40, n_tb=8)],
     "sync_ols_two_sb": [tiny("sync_ols", L=16, N=128, c=-20, ncp=CP_FRAC[:3] + [9, 9], n_sym=5),
                         tiny("sync_ols", L=32, N=128, c=25, ncp=CP_FRAC[:3] + [9, 9], n_sym=5, K=16, n_tb=4)],
+    # smooth outer window edges: short, and the longest the CP schedule allows
+    "sync_ols_taper_6": [tiny("sync_ols", ncp=CP_FRAC, taper=6)],
+    "sync_ols_taper_max": [tiny("sync_ols", ncp=CP_FRAC, taper=14)],
+    "sync_ols_taper_64_256": [tiny("sync_ols", L=64, N=256, c=-40, ncp=[20, 18, 18, 18, 20], K=40, n_tb=8,
+                                   taper=32)],
+    "sync_ols_taper_two_sb": [tiny("sync_ols", L=16, N=128, c=-20, ncp=CP_FRAC[:3] + [9, 9], taper=10),
+                              tiny("sync_ols", L=32, N=128, c=25, ncp=CP_FRAC[:3] + [9, 9], K=16, n_tb=4,
+                                   taper=10)],
 }
 
 
@@ -219,6 +227,7 @@ def run_tx_grid(subbands, io, seed=0, qam=16, weights="rc"):
 GRID = {
     "sync_ola_frac": TINY_TX["sync_ola_frac"],
     "sync_ols_64_256": TINY_TX["sync_ols_64_256"],
+    "sync_ols_taper_64_256": TINY_TX["sync_ols_taper_64_256"],
     "sync_ola_64_256": TINY_TX["sync_ola_64_256"],
     "two_sb_one_group": TINY_TX["two_sb_one_group"],
     "one_symbol": EDGE["one_symbol_sync"],
@@ -262,12 +271,14 @@ def test_mixed_numerology_tx(io):
     assert_gate(got, ref, io, "mixed numerology TX")
 
 
-def test_mixed_numerology_tx_sync_ols():
+@pytest.mark.parametrize("taper", [0, 64])
+def test_mixed_numerology_tx_sync_ols(taper):
     """Synchronised OLS TX of the two-numerology subframe (accumulating groups
-    on one stream)."""
+    on one stream), with hard and with smooth outer window edges."""
     sbs, meta = W.mixed_numerology("sync_ols")
+    sbs = [dict(s, taper=taper) for s in sbs]
     got, ref = run_tx(sbs, "c64", seed=meta["seed"], qam=meta["qam"])
-    assert_gate(got, ref, "c64", "mixed numerology sync OLS TX")
+    assert_gate(got, ref, "c64", "mixed numerology sync OLS TX, taper %d" % taper)
 
 
 def test_mixed_numerology_rx():

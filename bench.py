@@ -180,6 +180,17 @@ def rxd_cost(sbs):
     return flops
 
 
+def wgrad_cost(sbs):
+    """Flops of the weight gradient per call: per TX block the adjoint's long
+    FFT (5 N log2 N) and short IFFT, the forward short FFT of the input
+    (5 L log2 L each) and the bin-wise products (4 L)."""
+    flops = 0.0
+    for s in sbs:
+        L, N = s["n_short"], s["n_long"]
+        flops += 2 * s["n_symbols"] * (5 * N * math.log2(N) + 2 * 5 * L * math.log2(L) + 4 * L)
+    return flops
+
+
 def traffic(op):
     """HBM bytes per call of op from the committed rocprofv3 counter summary
     (profiles/traffic_<op>.json), or None when the kernel sources changed
@@ -232,9 +243,10 @@ def cpu_baseline(budget_s, tx_sbs, tx_meta, gpu_tx_out, tx_plan_one, rx_sbs, rx_
         if time.time() - t0 > budget_s * 0.6:
             break
     t_tx = time.time() - t0
-    # error split on the first few carriers: storage (oracle on the FP16-rounded
-    # input against the unquantised one) and compute (GPU against the oracle
-    # on the rounded input); and the distance to plain linear convolution
+    # first few carriers: out-of-band power ratio of GPU and FP64 outputs, and
+    # the error split: storage (oracle on the FP16-rounded input against the
+    # unquantised one), compute and output rounding (GPU against the oracle on
+    # the rounded input), and the distance to plain linear convolution
     split = []
     for k in order[:4]:
         s = dict(tx_sbs[k], stream=0)
@@ -243,7 +255,10 @@ def cpu_baseline(budget_s, tx_sbs, tx_meta, gpu_tx_out, tx_plan_one, rx_sbs, rx_
         ref_q = oracle_tx([s], [quantize(xs[k], tx_meta["io"])], D)[0]
         ref_lin = oracle_tx([s], [xs[k]], D, reference="lin")[0]
         got = gpu_tx_out[hi[k]:hi[k + 1]]
+        band = [(s["center_bin"], s["n_active"], s["n_tb"])]
         split.append(dict(carrier=int(k), L=s["n_short"], N=s["n_long"],
+                          oob_gpu=round(float(metrics.oob_ratio_db(got, s["n_long"], band)), 2),
+                          oob_fp64=round(float(metrics.oob_ratio_db(ref, s["n_long"], band)), 2),
                           storage=round(float(metrics.err_db(ref_q, ref)), 2),
                           compute_and_output=round(float(metrics.err_db(got, ref_q)), 2),
                           total=round(float(metrics.err_db(got, ref)), 2),
@@ -467,6 +482,32 @@ def main():
                        "(the OFDM IFFT is run for each of a symbol's two blocks)"}
     log("tx grid: %.3f ms (%.1f TFLOP/s)" % (txg_ms, tx_grid["achieved_tflops"]))
 
+    # the weight gradient through the adjoint (Sec. III: the output is linear
+    # in D) on the same TX workload: a seeded random cotangent of the output
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    g_dev = torch.randn((int(hi[-1]), 2), generator=gen, device=dev).to(torch.float16)
+    gw = torch.empty(sum(s["n_short"] for s in tx_all), dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        ptx.weight_grad(x_dev, g_dev, gw, gs)
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a0.record(gs)
+    for _ in range(args.steps):
+        ptx.weight_grad(x_dev, g_dev, gw, gs)
+    a1.record(gs)
+    torch.cuda.synchronize()
+    wg_ms = a0.elapsed_time(a1) / args.steps
+    wg_flops = wgrad_cost(tx_all)
+    weight_grad = {"ms": round(wg_ms, 4), "value": round(tx_samples / (wg_ms * 1e-3) / 1e6, 1),
+                   "unit": "Msamples/s (high-rate cotangent samples)",
+                   "achieved_tflops": round(wg_flops / wg_ms / 1e9, 2),
+                   "frac": round(wg_flops / wg_ms / 1e9 / ALU_PEAK_TFLOPS, 4), "algorithmic_flops": int(wg_flops),
+                   "form": "dJ/dD of all 8192 carrier-slots' weights from the input and a cotangent of the "
+                           "output (FP16), adjoint kernels + per-bin products"}
+    del g_dev
+    log("weight grad: %.3f ms (%.1f TFLOP/s)" % (wg_ms, weight_grad["achieved_tflops"]))
+
     # single-unit latency: one slot of the 256 carriers, one RX frame (graph
     # replays, median of 20)
     latency = None
@@ -561,7 +602,7 @@ def main():
                    "storage": "f16 (TX) / bf16 (RX) interleaved I/Q", "timing": "HIP graph replays, HIP events",
                    "tx_samples": tx_samples, "rx_samples": rx_samples, "tx_ms": round(tx_ms, 4),
                    "rx_ms": round(rx_ms, 4), "tuning": tune, "latency": latency},
-        "roofline": roof, "rx_demod": rx_demod, "tx_grid": tx_grid, "plain": plain, "evm_db": evm, "method_check": method,
+        "roofline": roof, "rx_demod": rx_demod, "tx_grid": tx_grid, "weight_grad": weight_grad, "plain": plain, "evm_db": evm, "method_check": method,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -72,6 +72,25 @@ def test_weight_grad_mixed_numerology_sampled():
     assert_grad(gpu_wgrad(sbs, xs, Ds, gs), ref, "mixed numerology", bins)
 
 
+def test_weight_grad_largest_carrier_sampled():
+    """The largest carrier shape of the batched TX (L = 2048 in N = 4096, one
+    slot, FP16 storage of input and cotangent), sampled bins."""
+    import torch
+    from fc_cases import quantize
+    s = W.subband(30, 14, 1272, 8, 2048, 4096, -700, "sync_ola")
+    xs, Ds, _ = make_inputs([s], 64, 31, "rc")
+    xq = [quantize(xs[0], "f16")]
+    gq = [quantize(_g_streams([s], 32)[0], "f16")]
+    L, K = 2048, 1272
+    bins = [sorted({(K // 2 - 1 + i + L // 2) % L for i in range(1, 9)} | {L // 2, L // 2 + 7})]
+    ref = oracle_wgrad([s], xq, gq, bins)
+    p = _plan([s], "f16", Ds)
+    gw = p.weight_grad(to_device(xq[0], "f16"), to_device(gq[0], "f16"))
+    torch.cuda.synchronize()
+    got = [gw.cpu().numpy().astype(np.float64)]
+    assert_grad(got, ref, "L 2048 N 4096 f16", bins)
+
+
 @pytest.mark.parametrize("name", ["cont_ols_16_64", "sync_ola_64_256", "two_sb_one_group"])
 def test_autograd_matches_oracle(name):
     """J = sum |y - t|^2 through fc_tx: grad_x against the oracle adjoint of

@@ -661,21 +661,45 @@ fc_status run_wgrad(fc_plan* P, const void* x, const void* g, float* grad_w, hip
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
   if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
-  fc_status result = FC_OK;
   // P->w_total floats (even: every L is a power of two >= 16) as complex zeros
-  if (launch_zero(grad_w, P->w_total / 2, IO_C64, st) != hipSuccess) result = FC_E_DEVICE;
-  for (const Op::Phase& ph : op.phases) {
-    if (result != FC_OK) break;
-    if (ph.kind == 2) continue;
+  hipError_t e = launch_zero(grad_w, P->w_total / 2, IO_C64, st);
+  auto launch = [&](const Op::Phase& ph, hipStream_t s) {
     LaunchArgs a{};
     a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
     a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
     a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
     a.in = g; a.out = grad_w; a.in2 = x;
-    if (launch_kernel(3, ph.size, a, ph.aux, ph.glds, st) != hipSuccess) result = FC_E_DEVICE;
+    return launch_kernel(3, ph.size, a, ph.aux, ph.glds, s);
+  };
+  // the adjoint's independent launch sets, spread over the side streams as
+  // run_op does (the kernels add into grad_w with atomics)
+  std::vector<const Op::Phase*> ph;
+  for (const Op::Phase& p : op.phases)
+    if (p.kind != 2) ph.push_back(&p);
+  for (size_t i = 0; i < ph.size() && e == hipSuccess;) {
+    size_t j = i + 1;
+    while (j < ph.size() && ph[j]->seq == ph[i]->seq) ++j;
+    const int ways = std::min<int>(P->conc[FC_OP_ADJ], (int)(j - i));
+    if (ways <= 1) {
+      for (size_t k = i; k < j && e == hipSuccess; ++k) e = launch(*ph[k], st);
+    } else {
+      e = hipEventRecord(P->ev_fork, st);
+      for (int q = 0; q + 1 < ways && e == hipSuccess; ++q) e = hipStreamWaitEvent(P->side[q], P->ev_fork, 0);
+      double load[kMaxConc] = {};
+      for (size_t k = i; k < j && e == hipSuccess; ++k) {
+        const int q = (int)(std::min_element(load, load + ways) - load);
+        load[q] += ph[k]->cost;
+        e = launch(*ph[k], q == 0 ? st : P->side[q - 1]);
+      }
+      for (int q = 0; q + 1 < ways && e == hipSuccess; ++q) {
+        e = hipEventRecord(P->ev_join[q], P->side[q]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, P->ev_join[q], 0);
+      }
+    }
+    i = j;
   }
   if (cur != P->device) (void)hipSetDevice(cur);
-  return result;
+  return e == hipSuccess ? FC_OK : FC_E_DEVICE;
 }
 
 // Measured schedule: times every kernel launch of the op on its own (one

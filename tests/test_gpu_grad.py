@@ -55,6 +55,33 @@ def test_weight_grad_tiny(name):
     assert_grad(gpu_wgrad(sbs, xs, Ds, gs), oracle_wgrad(sbs, xs, gs), name)
 
 
+# single-subband groups at larger interpolation factors: continuous OLS / OLA
+# (accumulating adjoint), a quarter overlap, I = 64, and L = 1024
+SINGLE = {
+    "cont_ols_64_256": W.subband(15, 3, 40, 8, 64, 256, -40, "cont_ols"),
+    "cont_ola_quarter_64_512": W.subband(15, 3, 40, 8, 64, 512, 50, "cont_ola", overlap=(1, 4)),
+    "sync_ola_16_1024": W.subband(15, 5, 8, 2, 16, 1024, -300, "sync_ola"),
+    "sync_ola_1024_2048": W.subband(15, 3, 600, 8, 1024, 2048, 200, "sync_ola"),
+}
+SINGLE_CP = {"cont_ols_64_256": [20, 16, 16], "cont_ola_quarter_64_512": [24, 16, 16]}
+
+
+@pytest.mark.parametrize("name", sorted(SINGLE))
+def test_weight_grad_single_subband(name):
+    s = dict(SINGLE[name])
+    if name in SINGLE_CP:
+        s["ncp_high"] = SINGLE_CP[name]
+    sbs = [s]
+    xs, Ds, _ = make_inputs(sbs, 16, 25, "random")
+    gs = _g_streams(sbs, 26)
+    L = s["n_short"]
+    bins = None
+    if L > 64:
+        rng = np.random.default_rng(27)
+        bins = [sorted(rng.choice(L, 12, replace=False).tolist())]
+    assert_grad(gpu_wgrad(sbs, xs, Ds, gs), oracle_wgrad(sbs, xs, gs, bins), name, bins)
+
+
 def test_weight_grad_mixed_numerology_sampled():
     """Both subbands of the 20 MHz mixed-numerology subframe; the oracle
     evaluates the transition bins and a seeded sample of the others."""

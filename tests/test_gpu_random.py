@@ -1,0 +1,82 @@
+"""Seeded random plans against the FP64 oracle: modes, sizes, centres,
+overlaps, smooth edges, CP schedules, and subbands sharing a stream.
+
+Each configuration is drawn from a fixed seed and kept only if a host-only
+plan accepts it (so every drawn case is one the library declares valid); the
+TX, the RX, and where the mode has them the adjoint and the demodulating RX
+are compared with the oracle under the FP32 gate."""
+import numpy as np
+import pytest
+
+from fc_cases import GATE_DB
+from fcsynth import workloads as W
+from test_gpu_parity import assert_gate, run_rx, run_tx
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["cont_ola", "cont_ols", "sync_ola", "sync_ols"]
+
+
+def draw(seed):
+    """One valid plan (list of subbands) from the seed."""
+    from paper_2008_00672_amd import FcError, Plan
+    rng = np.random.default_rng(seed)
+    while True:
+        mode = MODES[int(rng.integers(0, 4))]
+        sync = mode.startswith("sync")
+        n_sb = int(rng.integers(1, 4))
+        N = int(2 ** rng.integers(6, 11))                  # 64 .. 1024
+        n_sym = int(rng.integers(1, 5))
+        lam = (1, 2) if sync or rng.random() < 0.6 else (1, 4)
+        # one CP schedule per plan (subbands sharing a stream share it)
+        if sync:
+            ncp = [int(v) for v in rng.integers(1, N // 4, n_sym)]
+        else:
+            step = N // 16
+            ncp = [int(step * v) for v in rng.integers(1, 4, n_sym)]
+        taper = 0
+        if mode == "sync_ols" and rng.random() < 0.5:
+            taper = 2 * int(rng.integers(1, max(2, (N // 4 - max(ncp)) // 2 + 1)))
+        sbs = []
+        for m in range(n_sb):
+            L = int(min(N, 2 ** rng.integers(4, 9)))       # 16 .. 256
+            n_tb = int(rng.integers(0, 5))
+            K = 2 * int(rng.integers(0, (L - 2 * n_tb) // 2 + 1))
+            cmax = N // 2 - L // 2
+            c = int(rng.integers(-cmax, cmax + 1))
+            s = W.subband(15, n_sym, K, n_tb, L, N, c, mode, stream=0 if rng.random() < 0.7 else m,
+                          overlap=lam, taper=taper)
+            s["ncp_high"] = ncp
+            sbs.append(s)
+        # streams numbered densely
+        ids = sorted({s["stream"] for s in sbs})
+        for s in sbs:
+            s["stream"] = ids.index(s["stream"])
+        try:
+            Plan(sbs, device=-1)
+        except FcError:
+            continue
+        return sbs
+
+
+SEEDS = list(range(100, 124))
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_plan(seed):
+    sbs = draw(seed)
+    desc = ", ".join("%s L%d N%d c%d K%d tb%d B%d%s" % (s["mode"], s["n_short"], s["n_long"], s["center_bin"],
+                                                        s["n_active"], s["n_tb"], s["n_symbols"],
+                                                        " taper%d" % s["taper"] if s["taper"] else "")
+                     for s in sbs)
+    print("seed %d: %s" % (seed, desc), flush=True)
+    got, ref = run_tx(sbs, "c64", seed=seed, weights="random")
+    assert_gate(got, ref, "c64", "random TX %d" % seed)
+    got, ref = run_rx(sbs, "c64", seed=seed, weights="random")
+    assert_gate(got, ref, "c64", "random RX %d" % seed)
+    if all(s["mode"] != "sync_ols" for s in sbs):
+        got, ref = run_rx(sbs, "c64", seed=seed, weights="random", adjoint=True)
+        assert_gate(got, ref, "c64", "random adjoint %d" % seed)
+    if all(s["mode"].startswith("sync") for s in sbs):
+        got, ref = run_rx(sbs, "c64", seed=seed, weights="random", demod=True)
+        assert_gate(got, ref, "c64", "random demod RX %d" % seed)

@@ -8,7 +8,9 @@
  *     (Sec. III-B, block operators F^(OLA), F^(OLS); Sec. IV, G^(OLA), G^(OLS));
  *   - symbol-synchronised FC whose blocks align with every OFDM symbol and its
  *     NR cyclic prefix, with CP truncation/extrapolation (Sec. III-C..III-E)
- *     and the synchronised receiver with CP removal (Sec. IV);
+ *     and the synchronised receiver with CP removal (Sec. IV); the
+ *     synchronised transmitter as OLA or as OLS with hard or smoothed output
+ *     window edges (Sec. III-D);
  *   - the synchronised receiver with OFDM demodulation in the simplified
  *     joint form (Sec. V-A), the transmitter from QAM grids with the OFDM
  *     modulation in the kernels, the adjoint and the weight gradient, HIP

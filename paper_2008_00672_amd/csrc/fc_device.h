@@ -411,7 +411,7 @@ template <int IO> struct LoadSeg : NoPrefetch {
 // Input segment whose first-pass samples were loaded ahead of time (raw
 // storage words in registers): issue() starts the loads, typically while the
 // previous block is still being transformed; operator() converts on use.
-template <int IO, int NT, int P> struct LoadAhead : NoPrefetch {
+template <int IO, int NT, int P, int RM = 16> struct LoadAhead : NoPrefetch {
   using T = typename Io<IO>::T;
   T raw[16];
   unsigned valid;
@@ -425,7 +425,7 @@ template <int IO, int NT, int P> struct LoadAhead : NoPrefetch {
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         int i, b;
-        if (first_pos<NT, P, 0>(s, tid, i, b)) {
+        if (first_pos<NT, P, 0, RM>(s, tid, i, b)) {
           raw[s] = x[i];
           valid |= 1u << s;
         }
@@ -435,7 +435,7 @@ template <int IO, int NT, int P> struct LoadAhead : NoPrefetch {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       int i, b;
-      if (first_pos<NT, P, 0>(s, tid, i, b) && i >= lo && i < hi) {
+      if (first_pos<NT, P, 0, RM>(s, tid, i, b) && i >= lo && i < hi) {
         raw[s] = x[i];
         valid |= 1u << s;
       }
@@ -449,7 +449,7 @@ template <int IO, int NT, int P> struct LoadAhead : NoPrefetch {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       int i, b;
-      if (first_pos<NT, P, 0>(s, tid, i, b)) {
+      if (first_pos<NT, P, 0, RM>(s, tid, i, b)) {
         const int g = i < (K >> 1) ? i + (K >> 1) : (i >= P - (K >> 1) ? i - P + (K >> 1) : -1);
         if (g >= 0) {
           raw[s] = row[g];
@@ -500,13 +500,13 @@ struct LoadLds : NoPrefetch {
 // band, weighted by D[p] (p = (u + L/2) mod L, the fftshifted index) and the
 // block phase. The weights of this thread's output bins are fetched when the
 // transform starts.
-template <int NT, int L> struct StoreBand {
+template <int NT, int L, int RM = 16> struct StoreBand {
   float2* V; const float* D; float2 ph; int c;
   float d[16];
   __device__ __forceinline__ void prefetch(int tid) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int u = last_pos<NT, L, 0>(s, tid);
+      const int u = last_pos<NT, L, 0, RM>(s, tid);
       if (u >= 0) d[s] = D[(u + (L >> 1)) & (L - 1)];
     }
   }
@@ -717,9 +717,10 @@ __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void
   const int rtid = (tid + 64 * (int)(blockIdx.x & 3)) & (kThreads - 1);
   const int sid = kWaveShort ? tid & 63 : tid;          // index within the short FFT's threads
   constexpr int NTS = kWaveShort ? 64 : kThreads;
+  constexpr int RMS = kWaveShort ? 16 : radix_cap(L);      // short-FFT radix plan (all threads busy)
   float2* band = kWaveShort ? bands + wave * lds_elems(L) : buf;
   int64_t prev_end = INT64_MIN;
-  LoadAhead<IO, NTS, L> ld;
+  LoadAhead<IO, NTS, L, RMS> ld;
   if (wave < NB && wave < T.blk_count) {
     const BlockSb Z0 = a.bsb[a.blk[T.blk_first + wave].bs];
     if constexpr (FRONT) ld.issue_grid(at<IO>(a.in, Z0.x0), Z0.K, sid);
@@ -735,20 +736,20 @@ __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void
     __syncthreads();
     if (wave < nb) {
       const BlockSb Zw = a.bsb[a.blk[T.blk_first + g0 + wave].bs];
-      StoreBand<NTS, L> sb;
+      StoreBand<NTS, L, RMS> sb;
       sb.V = band; sb.D = D; sb.ph = make_float2(Zw.ph.x, Zw.ph.y); sb.c = S.c;
       if constexpr (FRONT) {
         // grid input: the symbol's OFDM IFFT in the band region, then the
         // block's short FFT from it
         StoreScaled sx;
         sx.buf = band; sx.scale = rsqrtf((float)L);
-        fft_run<NTS, L, 0, +1>(band, sid, ld, sx, twb);
+        fft_run<NTS, L, 0, +1, RMS>(band, sid, ld, sx, twb);
         group_sync<NTS>();
         LoadCyclic<L> lcy;
         lcy.x = band; lcy.lo = Zw.lo; lcy.hi = Zw.hi; lcy.shift = Zw.shift;
-        fft_run<NTS, L, 0, -1>(band, sid, lcy, sb, twb);
+        fft_run<NTS, L, 0, -1, RMS>(band, sid, lcy, sb, twb);
       } else {
-        fft_run<NTS, L, 0, -1>(band, sid, ld, sb, twb);
+        fft_run<NTS, L, 0, -1, RMS>(band, sid, ld, sb, twb);
       }
     }
     // start loading the next group's inputs while this group's IFFTs run
@@ -822,15 +823,15 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
             lg.row = at<IO>(a.in, Z.x0); lg.K = Z.K;
             StoreScaled sx;
             sx.buf = bs; sx.scale = rsqrtf((float)LL);
-            fft_run<kThreads, LL, 0, +1>(bs, tid, lg, sx, tw);
+            fft_run<kThreads, LL, 0, +1, radix_cap(LL)>(bs, tid, lg, sx, tw);
             __syncthreads();
             LoadCyclic<LL> lcy;
             lcy.x = bs; lcy.lo = Z.lo; lcy.hi = Z.hi; lcy.shift = Z.shift;
-            fft_run<kThreads, LL, 0, -1>(bs, tid, lcy, st, tw);
+            fft_run<kThreads, LL, 0, -1, radix_cap(LL)>(bs, tid, lcy, st, tw);
           } else {
             LoadSeg<IO> ld;
             ld.x = at<IO>(a.in, Z.x0); ld.lo = Z.lo; ld.hi = Z.hi;
-            fft_run<kThreads, LL, 0, -1>(bs, tid, ld, st, tw);
+            fft_run<kThreads, LL, 0, -1, radix_cap(LL)>(bs, tid, ld, st, tw);
           }
         }
       }
@@ -844,9 +845,10 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
     TxEpiWin ep;
     ep.pend = pend; ep.pth = w.pth;
     ep.set_window(B.win, G.taper);
-    fft_run<kThreads, NL, 0, +1>(S, tid, ls, ep, tw);
+    fft_run<kThreads, NL, 0, +1, radix_cap(NL)>(S, tid, ls, ep, tw);
     __syncthreads();
-    tx_epilogue<IO, kThreads, NL, 0>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0, (int)threadIdx.x);
+    tx_epilogue<IO, kThreads, NL, 0, radix_cap(NL)>(ep, pend, w, at<IO>(a.out, B.t0), T.accumulate != 0,
+                                                     (int)threadIdx.x);
     prev_end = T.ola ? B.t0 + NL : INT64_MIN;
   }
 }
@@ -877,7 +879,7 @@ __global__ __launch_bounds__(kThreads, 4) void fc_rx_kernel(LaunchArgs a, int) {
   const int wave = ((tid >> 6) + blockIdx.x) & 3;
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const uint64_t* map = a.rxmap + G.map_off;
-  LoadAhead<IO, kThreads, NL> lh;
+  LoadAhead<IO, kThreads, NL, radix_cap(NL)> lh;
   {
     const BlockDesc B0 = a.blk[T.blk_first];
     lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
@@ -887,7 +889,7 @@ __global__ __launch_bounds__(kThreads, 4) void fc_rx_kernel(LaunchArgs a, int) {
     StoreScatter sc;
     sc.S = S; sc.map = map;
     __syncthreads();
-    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sc, tw);
+    fft_run<kThreads, NL, 0, -1, radix_cap(NL)>(S, tid, lh, sc, tw);
     if (bi + 1 < T.blk_count) {
       const BlockDesc Bn = a.blk[T.blk_first + bi + 1];
       lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
@@ -922,7 +924,7 @@ __global__ __launch_bounds__(kThreads, 4) void fc_rx_kernel(LaunchArgs a, int) {
           LoadCompact<kThreads, LL> lc2;
           lc2.R = S + Sb.cofs; lc2.D = a.weights + Sb.w_off; lc2.ph = make_float2(Z.ph.x, Z.ph.y);
           __syncthreads();
-          fft_run<kThreads, LL, 0, +1>(S + Sb.cofs, tid, lc2, so, tw);
+          fft_run<kThreads, LL, 0, +1, radix_cap(LL)>(S + Sb.cofs, tid, lc2, so, tw);
         }
       }
     };
@@ -1015,7 +1017,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
   const int wave = ((tid >> 6) + blockIdx.x) & 3;
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const uint64_t* map = a.rxmap + G.map_off;
-  LoadAhead<IO, kThreads, NL> lh;
+  LoadAhead<IO, kThreads, NL, radix_cap(NL)> lh;
   {
     const BlockDesc B0 = a.blk[T.blk_first];
     lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
@@ -1027,7 +1029,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
     sc.S = S; sc.map = map;
     // ---- first block: spectrum -> regions -> A
     __syncthreads();
-    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sc, tw);
+    fft_run<kThreads, NL, 0, -1, radix_cap(NL)>(S, tid, lh, sc, tw);
     lh.issue(at<IO>(a.in, B1.t0), B1.hlo, B1.hhi, tid);
     __syncthreads();
     for (int m = 0; m < G.n_sb; ++m) {
@@ -1046,7 +1048,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
     }
     __syncthreads();
     // ---- second block: spectrum -> regions; per subband the joint transform
-    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sc, tw);
+    fft_run<kThreads, NL, 0, -1, radix_cap(NL)>(S, tid, lh, sc, tw);
     if (bi + 2 < T.blk_count) {
       const BlockDesc Bn = a.blk[T.blk_first + bi + 2];
       lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
@@ -1150,7 +1152,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const uint64_t* map = a.rxmap + G.map_off;
   for (int i = tid; i < G.acc_len; i += kThreads) acc[i] = 0.f;
-  LoadAhead<IO, kThreads, NL> lh;
+  LoadAhead<IO, kThreads, NL, radix_cap(NL)> lh;
   {
     const BlockDesc B0 = a.blk[T.blk_first];
     lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
@@ -1160,7 +1162,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
     StoreScatter sc;
     sc.S = S; sc.map = map;
     __syncthreads();
-    fft_run<kThreads, NL, 0, -1>(S, tid, lh, sc, tw);
+    fft_run<kThreads, NL, 0, -1, radix_cap(NL)>(S, tid, lh, sc, tw);
     if (bi + 1 < T.blk_count) {
       const BlockDesc Bn = a.blk[T.blk_first + bi + 1];
       lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
@@ -1196,7 +1198,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
           StoreGrad sg;
           sg.R = S + Sb.cofs; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = acc + Sb.aofs;
           __syncthreads();
-          fft_run<kThreads, LL, 0, -1>(scr, tid, ls, sg, tw);
+          fft_run<kThreads, LL, 0, -1, radix_cap(LL)>(scr, tid, ls, sg, tw);
         }
       }
     };

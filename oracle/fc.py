@@ -218,7 +218,9 @@ def taper_ramp(T):
     """Rising edge of T samples, w_i = sin^2(pi (i + 1/2) / (2T)), i = 0..T-1.
     Sec. III-D asks for a smooth edge without giving its shape; this raised
     cosine is symmetric about its midpoint, so the falling edge w_{T-1-i}
-    equals 1 - w_i and the two edges of neighbouring symbols cross-fade."""
+    equals 1 - w_i and the two edges of neighbouring symbols cross-fade.
+    The shape itself is a reading: pinned only through that cross-fade
+    property and the leakage it removes (parity unpinned beyond them)."""
     i = np.arange(T)
     return np.sin(np.pi * (i + 0.5) / (2 * T)) ** 2
 

@@ -19,11 +19,15 @@ enum IoType : int32_t { IO_C64 = 0, IO_F16 = 1, IO_BF16 = 2 };
 constexpr int lds_elems(int n) { return n + (n >> 5); }
 
 // TX pruned kernel, L <= 1024: blocks whose short FFTs run at once (one per
-// wave), the most of {4, 2, 1} whose LDS (long IFFT buffer, OLA carry, one
-// band region per block) still lets two workgroups share a CU.
+// wave). LDS: long IFFT buffer, OLA carry, one band region per block. Four
+// or three blocks where that lets three workgroups share a CU (one idle wave
+// in the short-FFT phase costs less than a third workgroup gains), else the
+// most of {4, 2, 1} that lets two share it.
 constexpr int pruned_lds_entries(int L, int N, int nb) { return lds_elems(N) + N / 2 + nb * lds_elems(L); }
 constexpr int pruned_group_blocks(int L, int N) {
   return L > 1024 ? 1
+         : pruned_lds_entries(L, N, 4) * 8 <= 163840 / 3 ? 4
+         : pruned_lds_entries(L, N, 3) * 8 <= 163840 / 3 ? 3
          : pruned_lds_entries(L, N, 4) * 8 <= 80 * 1024 ? 4
          : pruned_lds_entries(L, N, 2) * 8 <= 80 * 1024 ? 2 : 1;
 }

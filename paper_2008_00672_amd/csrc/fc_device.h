@@ -1151,12 +1151,61 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
   const int wave = ((tid >> 6) + blockIdx.x) & 3;
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const uint64_t* map = a.rxmap + G.map_off;
-  for (int i = tid; i < G.acc_len; i += kThreads) acc[i] = 0.f;
   LoadAhead<IO, kThreads, NL, radix_cap(NL)> lh;
   {
     const BlockDesc B0 = a.blk[T.blk_first];
     lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
   }
+  if (G.wg_nb > 0) {
+    // one subband, L <= 1024: the long FFTs of a group of blocks scatter into
+    // one band region each, then every wave runs the short FFT of one
+    // block's forward input against its region, with its own accumulators
+    const SbDesc Sb = a.sb[G.sb_first];
+    const int L = Sb.L, NBG = G.wg_nb, le = lds_elems(L);
+    float2* reg = S + lds_elems(NL);
+    float2* sbuf = reg + NBG * le;
+    float* gacc = reinterpret_cast<float*>(sbuf + NBG * le);
+    for (int i = tid; i < NBG * L; i += kThreads) gacc[i] = 0.f;
+    for (int g0 = 0; g0 < T.blk_count; g0 += NBG) {
+      const int nb = T.blk_count - g0 < NBG ? T.blk_count - g0 : NBG;
+      for (int k = 0; k < nb; ++k) {
+        StoreScatter sc;
+        sc.S = reg + k * le; sc.map = map;
+        __syncthreads();
+        fft_run<kThreads, NL, 0, -1, radix_cap(NL)>(S, tid, lh, sc, tw);
+        if (g0 + k + 1 < T.blk_count) {
+          const BlockDesc Bn = a.blk[T.blk_first + g0 + k + 1];
+          lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
+        }
+      }
+      __syncthreads();
+      if (wave < nb) {
+        const BlockSb Z = a.bsb[a.blk[T.blk_first + g0 + wave].bs];
+        auto run = [&](auto lc) {
+          constexpr int LL = decltype(lc)::value;
+          if constexpr (LL <= NL) {
+            if (L != LL) return;
+            LoadSeg<IO> ls;
+            ls.x = at<IO>(a.in2, Z.x0); ls.lo = Z.lo; ls.hi = Z.hi;
+            StoreGrad sg;
+            sg.R = reg + wave * le; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = gacc + wave * L;
+            fft_run<64, LL, 0, -1>(sbuf + wave * le, lane, ls, sg, tw);
+          }
+        };
+        run(SizeC<1024>()); run(SizeC<512>()); run(SizeC<256>()); run(SizeC<128>());
+        run(SizeC<64>()); run(SizeC<32>()); run(SizeC<16>());
+      }
+    }
+    __syncthreads();
+    float* gw = reinterpret_cast<float*>(a.out);
+    for (int u = tid; u < L; u += kThreads) {
+      float sum = 0.f;
+      for (int w = 0; w < NBG; ++w) sum += gacc[w * L + u];
+      atomicAdd(gw + Sb.w_off + ((u + (L >> 1)) & (L - 1)), sum);
+    }
+    return;
+  }
+  for (int i = tid; i < G.acc_len; i += kThreads) acc[i] = 0.f;
   for (int bi = 0; bi < T.blk_count; ++bi) {
     const BlockDesc B = a.blk[T.blk_first + bi];
     StoreScatter sc;

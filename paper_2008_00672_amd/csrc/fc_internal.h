@@ -41,6 +41,15 @@ constexpr int pruned_waves_per_simd(int L, int N) {
   return 163840 / pruned_lds_bytes(L, N) >= 3 ? 3 : 163840 / pruned_lds_bytes(L, N);
 }
 
+// Weight gradient of a one-subband group with L <= 1024, blocks in groups:
+// long-FFT buffer, then per block of a group its band region, its short-FFT
+// buffer and L float accumulators; the most of {4, 2, 1} blocks within
+// 80 KiB (two workgroups per CU).
+constexpr int wgg_lds_entries(int L, int N, int nb) { return lds_elems(N) + 2 * nb * lds_elems(L) + nb * L / 2; }
+constexpr int wgg_group_blocks(int L, int N) {
+  return wgg_lds_entries(L, N, 4) * 8 <= 80 * 1024 ? 4 : wgg_lds_entries(L, N, 2) * 8 <= 80 * 1024 ? 2 : 1;
+}
+
 struct Cf {   // complex float with the same layout as HIP's float2
   float x, y;
 };
@@ -129,6 +138,8 @@ struct GroupDesc {
   int32_t acc_off;           // weight gradient: LDS offset (complex entries) of the accumulators
   int32_t acc_len;           // weight gradient: accumulator floats (sum of the subbands' L)
   int32_t taper;             // TX, synchronised OLS: edge length T of the output windows (0: hard edges)
+  int32_t wg_nb;             // weight gradient, one subband with L <= 1024: blocks per group (0: per block)
+  int32_t pad2;
 };
 
 // One FC block of a group.

@@ -362,6 +362,9 @@ void build_op(fc_plan* P, int kind) {
       gr.wstride = wmax ? lds_elems(wmax) : 0;
       gr.scr_off = std::max(lds_elems(gr.N), rsum);
       gr.acc_off = gr.scr_off + std::max(4 * gr.wstride, lmax_long ? lds_elems(lmax_long) : 0);
+      // one subband with a one-wave short transform: the gradient takes its
+      // blocks in groups, one short FFT per wave (instead of one wave busy)
+      if (gr.n_sb == 1 && wmax > 0) gr.wg_nb = wgg_group_blocks(wmax, gr.N);
     }
   }
   // blocks and tasks; tasks are collected per launch phase and kernel class
@@ -535,7 +538,8 @@ void build_op(fc_plan* P, int kind) {
         // block's spectra while the second block's long FFT runs
         ct.lds = std::max(ct.lds, (size_t)(std::max(lds_elems(N), lsum) + (kind == 3 ? lsum : 0)) * 8);
         const GroupDesc& gd = op.grp[g];
-        ct.glds = std::max(ct.glds, (size_t)(gd.acc_off + (gd.acc_len + 1) / 2) * 8);
+        ct.glds = std::max(ct.glds, gd.wg_nb ? (size_t)wgg_lds_entries(lmax, N, gd.wg_nb) * 8
+                                              : (size_t)(gd.acc_off + (gd.acc_len + 1) / 2) * 8);
       }
     }
   }

@@ -678,15 +678,16 @@ __device__ __forceinline__ void zero_span(void* out, int64_t lo, int64_t hi) {
 
 // Single-subband group, N = L * 2^LOGI: short FFT, then the long IFFT
 // evaluated as 2^LOGI interleaved L-point IFFTs of the twiddled band (outputs
-// land in natural order). With L <= 1024 the blocks go in groups of up to
-// four: each wave runs the short FFT of one block of the group into its own
-// band region, then the workgroup runs the group's long IFFTs and epilogues
-// in block order (the OLA carry passes from block to block through LDS).
-// Larger L: one block at a time, the short FFT on the whole workgroup.
+// land in natural order). Where pruned_wave_short(L, N) holds, the blocks go
+// in groups of up to four: each wave runs the short FFT of one block of the
+// group into its own band region, then the workgroup runs the group's long
+// IFFTs and epilogues in block order (the OLA carry passes from block to
+// block through LDS). Otherwise one block at a time, the short FFT on the
+// whole workgroup in the long IFFT buffer.
 template <int IO, int L, int LOGI, bool FRONT>
 __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void fc_tx_pruned_kernel(LaunchArgs a) {
   constexpr int N = L << LOGI;
-  constexpr bool kWaveShort = L <= 1024;
+  constexpr bool kWaveShort = pruned_wave_short(L, L << LOGI);
   constexpr int NB = pruned_group_blocks(L, N);             // blocks per group
   // the long IFFT's first-pass twiddles depend only on the thread and the
   // subband: fetched once per task and kept in registers where the LDS

@@ -18,21 +18,26 @@ enum IoType : int32_t { IO_C64 = 0, IO_F16 = 1, IO_BF16 = 2 };
 // the device code's pad()).
 constexpr int lds_elems(int n) { return n + (n >> 5); }
 
-// TX pruned kernel, L <= 1024: blocks whose short FFTs run at once (one per
-// wave). LDS: long IFFT buffer, OLA carry, one band region per block. Four
-// or three blocks where that lets three workgroups share a CU (one idle wave
-// in the short-FFT phase costs less than a third workgroup gains), else the
-// most of {4, 2, 1} that lets two share it.
+// TX pruned kernel. Short FFTs one per wave (blocks in groups, one band
+// region each) for L < 256 and for N <= 1024; otherwise on the whole
+// workgroup in the long IFFT buffer, one block at a time: that frees the
+// band regions' LDS, and the extra workgroups per CU outweigh the smaller
+// per-wave transforms (measured on the batched TX: 2.07 against 2.27 ms).
+// Grouped blocks: LDS = long IFFT buffer, OLA carry, one band region per
+// block; four or three blocks where that lets three workgroups share a CU
+// (one idle wave in the short-FFT phase costs less than a third workgroup
+// gains), else the most of {4, 2, 1} that lets two share it.
 constexpr int pruned_lds_entries(int L, int N, int nb) { return lds_elems(N) + N / 2 + nb * lds_elems(L); }
+constexpr bool pruned_wave_short(int L, int N) { return L < 256 || (L <= 1024 && N < 2048); }
 constexpr int pruned_group_blocks(int L, int N) {
-  return L > 1024 ? 1
+  return !pruned_wave_short(L, N) ? 1
          : pruned_lds_entries(L, N, 4) * 8 <= 163840 / 3 ? 4
          : pruned_lds_entries(L, N, 3) * 8 <= 163840 / 3 ? 3
          : pruned_lds_entries(L, N, 4) * 8 <= 80 * 1024 ? 4
          : pruned_lds_entries(L, N, 2) * 8 <= 80 * 1024 ? 2 : 1;
 }
 constexpr int pruned_lds_bytes(int L, int N) {
-  return pruned_lds_entries(L, N, L <= 1024 ? pruned_group_blocks(L, N) : 0) * 8;
+  return pruned_lds_entries(L, N, pruned_wave_short(L, N) ? pruned_group_blocks(L, N) : 0) * 8;
 }
 // Workgroups per CU that the LDS allows (160 KiB per CU), at most three: the
 // register budget follows, so that registers do not lower the occupancy the

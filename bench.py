@@ -360,6 +360,7 @@ def main():
     tx_one, tx_all, tx_meta = tx_workload(args.tx_batches)
     t = time.time()
     ptx = Plan(tx_all, io="f16", device=0)
+    plan_s = {"tx": round(time.time() - t, 3)}
     ptx1 = Plan(tx_one, io="f16", device=0)
     xs = tx_input(ptx1, tx_one, tx_meta)
     x_dev = to_dev(np.concatenate(xs), "f16", reps=args.tx_batches)
@@ -372,6 +373,7 @@ def main():
     rx_one, rx_all, rx_meta = rx_workload(args.rx_frames)
     t = time.time()
     prx = Plan(rx_all, io="bf16", device=0)
+    plan_s["rx"] = round(time.time() - t, 3)
     prx1 = Plan(rx_one, io="bf16", device=0)
     rx_in = rx_input(prx1, rx_one, rx_meta)
     r_dev = to_dev(rx_in, "bf16", reps=args.rx_frames)
@@ -618,6 +620,7 @@ def main():
                                % (args.tx_batches, args.rx_frames),
                    "storage": "f16 (TX) / bf16 (RX) interleaved I/Q", "timing": "HIP graph replays, HIP events",
                    "tx_samples": tx_samples, "rx_samples": rx_samples, "tx_ms": round(tx_ms, 4),
+                   "plan_create_s": plan_s,
                    "rx_ms": round(rx_ms, 4), "tuning": tune, "latency": latency},
         "roofline": roof, "rx_demod": rx_demod, "tx_grid": tx_grid, "weight_grad": weight_grad, "plain": plain, "evm_db": evm, "method_check": method,
         "cpu_baseline": cpu,

@@ -373,6 +373,8 @@ void build_op(fc_plan* P, int kind) {
   std::map<int, PhaseTasks> tx_phase;        // TX: by group rank within the stream
   PhaseTasks rx_all, rx_even, rx_odd;
   bool any_acc_tx = false, any_ola_rx = false;
+  int64_t total_blocks = 0;
+  for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
   for (size_t g = 0; g < ogroups.size(); ++g) {
     const OpGroup& OG = ogroups[g];
     const Group& G = P->groups[OG.pg];
@@ -473,8 +475,6 @@ void build_op(fc_plan* P, int kind) {
           std::count_if(P->groups.begin(), P->groups.end(), [&](const Group& o) { return o.stream == G.stream; }) > 1;
       any_acc_tx |= acc;
       const bool ola = G.ola || G.taper > 0;
-      int64_t total_blocks = 0;
-      for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
       int K = P->run_len[0] > 0 ? P->run_len[0]
                                 : (int)std::max<int64_t>(8, std::min<int64_t>(64, total_blocks / 2048));
       if (G.sync) K += K & 1;                           // whole symbols per run
@@ -521,8 +521,6 @@ void build_op(fc_plan* P, int kind) {
       // launch add into the same low-rate samples ---
       const bool acc = !G.sync && ((kind == 1 && G.ola) || (kind == 2 && !G.ola));
       any_ola_rx |= acc;
-      int64_t total_blocks = 0;
-      for (const Group& o : P->groups) total_blocks += o.sync ? 2 * P->subs[o.subs[0]].d.n_symbols : o.R;
       int K = acc ? 1
                   : P->run_len[kind] > 0 ? P->run_len[kind]
                                          : (int)std::max<int64_t>(2, std::min<int64_t>(8, total_blocks / 4096));

@@ -415,17 +415,21 @@ template <int IO, int NT, int P, int RM = 16> struct LoadAhead : NoPrefetch {
   using T = typename Io<IO>::T;
   T raw[16];
   unsigned valid;
-  __device__ __forceinline__ void issue(const T* x, int lo, int hi, int tid) {
+  __device__ __forceinline__ void issue(const T* x, int lo, int hi, int tid) { issue_sized<P>(x, lo, hi, tid); }
+  // The same for a PP-point transform (the slots' layout does not depend on
+  // the size, so one object can serve transforms of a size known at run time).
+  template <int PP>
+  __device__ __forceinline__ void issue_sized(const T* x, int lo, int hi, int tid) {
     // keep the loads where they are issued: hoisted above the transform that
     // precedes them they would only lengthen register live ranges
     asm volatile("" : "+v"(tid) : : "memory");
     valid = 0;
-    if (lo <= 0 && hi >= P) {
+    if (lo <= 0 && hi >= PP) {
       // the whole block is valid (a uniform branch): no per-sample checks
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         int i, b;
-        if (first_pos<NT, P, 0, RM>(s, tid, i, b)) {
+        if (first_pos<NT, PP, 0, RM>(s, tid, i, b)) {
           raw[s] = x[i];
           valid |= 1u << s;
         }
@@ -435,7 +439,7 @@ template <int IO, int NT, int P, int RM = 16> struct LoadAhead : NoPrefetch {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       int i, b;
-      if (first_pos<NT, P, 0, RM>(s, tid, i, b) && i >= lo && i < hi) {
+      if (first_pos<NT, PP, 0, RM>(s, tid, i, b) && i >= lo && i < hi) {
         raw[s] = x[i];
         valid |= 1u << s;
       }
@@ -1167,8 +1171,22 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
     float2* sbuf = reg + NBG * le;
     float* gacc = reinterpret_cast<float*>(sbuf + NBG * le);
     for (int i = tid; i < NBG * L; i += kThreads) gacc[i] = 0.f;
+    // this wave's forward-input block of the group, loaded while the group's
+    // long FFTs run
+    LoadAhead<IO, 64, 1024> lx;
     for (int g0 = 0; g0 < T.blk_count; g0 += NBG) {
       const int nb = T.blk_count - g0 < NBG ? T.blk_count - g0 : NBG;
+      if (wave < nb) {
+        const BlockSb Z = a.bsb[a.blk[T.blk_first + g0 + wave].bs];
+        auto issue = [&](auto lc) {
+          constexpr int LL = decltype(lc)::value;
+          if constexpr (LL <= NL) {
+            if (L == LL) lx.template issue_sized<LL>(at<IO>(a.in2, Z.x0), Z.lo, Z.hi, lane);
+          }
+        };
+        issue(SizeC<1024>()); issue(SizeC<512>()); issue(SizeC<256>()); issue(SizeC<128>());
+        issue(SizeC<64>()); issue(SizeC<32>()); issue(SizeC<16>());
+      }
       for (int k = 0; k < nb; ++k) {
         StoreScatter sc;
         sc.S = reg + k * le; sc.map = map;
@@ -1186,11 +1204,9 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
           constexpr int LL = decltype(lc)::value;
           if constexpr (LL <= NL) {
             if (L != LL) return;
-            LoadSeg<IO> ls;
-            ls.x = at<IO>(a.in2, Z.x0); ls.lo = Z.lo; ls.hi = Z.hi;
             StoreGrad sg;
             sg.R = reg + wave * le; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = gacc + wave * L;
-            fft_run<64, LL, 0, -1>(sbuf + wave * le, lane, ls, sg, tw);
+            fft_run<64, LL, 0, -1>(sbuf + wave * le, lane, lx, sg, tw);
           }
         };
         run(SizeC<1024>()); run(SizeC<512>()); run(SizeC<256>()); run(SizeC<128>());

@@ -415,10 +415,11 @@ template <int IO, int NT, int P, int RM = 16> struct LoadAhead : NoPrefetch {
   using T = typename Io<IO>::T;
   T raw[16];
   unsigned valid;
-  __device__ __forceinline__ void issue(const T* x, int lo, int hi, int tid) { issue_sized<P>(x, lo, hi, tid); }
-  // The same for a PP-point transform (the slots' layout does not depend on
-  // the size, so one object can serve transforms of a size known at run time).
-  template <int PP>
+  __device__ __forceinline__ void issue(const T* x, int lo, int hi, int tid) { issue_sized<P, RM>(x, lo, hi, tid); }
+  // The same for a PP-point transform with radix plan RMM (the slots' layout
+  // does not depend on them, so one object can serve transforms of a size
+  // known at run time).
+  template <int PP, int RMM = 16>
   __device__ __forceinline__ void issue_sized(const T* x, int lo, int hi, int tid) {
     // keep the loads where they are issued: hoisted above the transform that
     // precedes them they would only lengthen register live ranges
@@ -429,7 +430,7 @@ template <int IO, int NT, int P, int RM = 16> struct LoadAhead : NoPrefetch {
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         int i, b;
-        if (first_pos<NT, PP, 0, RM>(s, tid, i, b)) {
+        if (first_pos<NT, PP, 0, RMM>(s, tid, i, b)) {
           raw[s] = x[i];
           valid |= 1u << s;
         }
@@ -439,7 +440,7 @@ template <int IO, int NT, int P, int RM = 16> struct LoadAhead : NoPrefetch {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       int i, b;
-      if (first_pos<NT, PP, 0, RM>(s, tid, i, b) && i >= lo && i < hi) {
+      if (first_pos<NT, PP, 0, RMM>(s, tid, i, b) && i >= lo && i < hi) {
         raw[s] = x[i];
         valid |= 1u << s;
       }
@@ -1223,8 +1224,22 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
     return;
   }
   for (int i = tid; i < G.acc_len; i += kThreads) acc[i] = 0.f;
+  // one subband with a whole-workgroup short FFT (L > 1024): its forward
+  // input block is loaded while the block's long FFT runs
+  const bool xpre = G.n_sb == 1 && G.n_long_sb == 1;
+  LoadAhead<IO, kThreads, 4096> lxl;
   for (int bi = 0; bi < T.blk_count; ++bi) {
     const BlockDesc B = a.blk[T.blk_first + bi];
+    if (xpre) {
+      const BlockSb Z = a.bsb[B.bs];
+      const int L1 = a.sb[G.sb_first].L;
+      if constexpr (NL >= 2048) {
+        if (L1 == 2048) lxl.template issue_sized<2048, radix_cap(2048)>(at<IO>(a.in2, Z.x0), Z.lo, Z.hi, tid);
+      }
+      if constexpr (NL >= 4096) {
+        if (L1 == 4096) lxl.template issue_sized<4096, radix_cap(4096)>(at<IO>(a.in2, Z.x0), Z.lo, Z.hi, tid);
+      }
+    }
     StoreScatter sc;
     sc.S = S; sc.map = map;
     __syncthreads();
@@ -1259,12 +1274,16 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave >= 0) continue;
           const BlockSb Z = a.bsb[B.bs + m];
-          LoadSeg<IO> ls;
-          ls.x = at<IO>(a.in2, Z.x0); ls.lo = Z.lo; ls.hi = Z.hi;
           StoreGrad sg;
           sg.R = S + Sb.cofs; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = acc + Sb.aofs;
           __syncthreads();
-          fft_run<kThreads, LL, 0, -1, radix_cap(LL)>(scr, tid, ls, sg, tw);
+          if (xpre) {
+            fft_run<kThreads, LL, 0, -1, radix_cap(LL)>(scr, tid, lxl, sg, tw);
+          } else {
+            LoadSeg<IO> ls;
+            ls.x = at<IO>(a.in2, Z.x0); ls.lo = Z.lo; ls.hi = Z.hi;
+            fft_run<kThreads, LL, 0, -1, radix_cap(LL)>(scr, tid, ls, sg, tw);
+          }
         }
       }
     };

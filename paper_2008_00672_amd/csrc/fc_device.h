@@ -1,7 +1,7 @@
 // Device code of the fast-convolution (FC) filter banks for gfx950.
 //
 // One workgroup (256 threads, 4 wave64) processes one task: a run of
-// consecutive FC blocks of one processing group (TX) or one block (RX).
+// consecutive FC blocks of one processing group.
 // Transforms are Stockham FFTs held in LDS: every pass loads R values per
 // butterfly into registers, applies the inter-pass twiddles (FP32 table built
 // in FP64 on the host), runs a radix-R (2/4/8/16) DFT in registers and writes
@@ -708,17 +708,17 @@ __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void
     zero_span<IO>(a.out, T.z1_lo, T.z1_hi);
   }
   const SbDesc S = a.sb[G.sb_first];
-  float2* buf = smem;                         // long IFFT (and, L > 1024, short FFT and band)
+  float2* buf = smem;                         // long IFFT (and, not kWaveShort, short FFT and band)
   float2* pend = smem + lds_elems(N);         // OLA carry, up to N/2 points
-  float2* bands = pend + N / 2;               // L <= 1024: one short-FFT / band region per wave
+  float2* bands = pend + N / 2;               // kWaveShort: one short-FFT / band region per wave
   const float* D = a.weights + S.w_off;
   const float2* tw = reinterpret_cast<const float2*>(a.twiddle);
   const float2* twb = reinterpret_cast<const float2*>(a.twpass);
   const int tid = threadIdx.x;
   const int wave = kWaveShort ? tid >> 6 : 0;             // waves >= NB idle in the short phase
-  // below N = 4096 the long IFFT's radix-16 passes keep N/16 threads busy:
-  // rotating the thread roles with the workgroup index spreads those threads'
-  // waves over the CU's SIMDs instead of loading the first SIMD(s) in every
+  // for N <= 512 even radix-4 passes keep only N/4 threads busy: rotating
+  // the thread roles with the workgroup index spreads those threads' waves
+  // over the CU's SIMDs instead of loading the first SIMD(s) in every
   // workgroup
   const int rtid = (tid + 64 * (int)(blockIdx.x & 3)) & (kThreads - 1);
   const int sid = kWaveShort ? tid & 63 : tid;          // index within the short FFT's threads
@@ -863,9 +863,10 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
 // A run of consecutive blocks per task. Per block: the long FFT on the whole
 // workgroup, whose last pass scatters every bin into the LDS region of each
 // subband that gathers it (inverse-shift order; the regions overlay the
-// spectrum); then each subband's short IFFT runs in place in its region: subbands with L <= 1024 as one-wave transforms on the wave the
-// planner chose, longer ones on the whole workgroup. The next block's input
-// is loaded into registers while the subbands run.
+// spectrum); then each subband's short IFFT runs in place in its region:
+// subbands with L <= 1024 as one-wave transforms on the wave the planner
+// chose, longer ones on the whole workgroup. The next block's input is
+// loaded into registers while the subbands run.
 template <int IO, int NL>
 __global__ __launch_bounds__(kThreads, 4) void fc_rx_kernel(LaunchArgs a, int) {
   extern __shared__ float2 smem[];

@@ -270,8 +270,10 @@ fc_status fc_tx_adjoint(fc_plan* plan, const void* highrate_in, void* lowrate_ou
  *               X the block's short FFT of x, G the long FFT of the matching
  *               block of g scaled like the adjoint, q = Xi(p).
  * Buffers are owned by the caller. Asynchronous on `stream`; the result does
- * not depend on the plan's current weights. Errors: FC_E_ARG (null pointer), FC_E_STATE
- * (host-only plan, or a plan with an FC_SYNC_OLS subband, which has no TX),
+ * not depend on the plan's current weights. Scheduled as the adjoint: the
+ * FC_OP_ADJ tuning (fc_plan_set_tuning) sets its blocks per task and its
+ * launches in flight. Errors: FC_E_ARG (null pointer), FC_E_STATE (host-only
+ * plan, or a plan with an FC_SYNC_OLS subband, which has no adjoint),
  * FC_E_DEVICE (launch failure).
  */
 fc_status fc_tx_weight_grad(fc_plan* plan, const void* lowrate_in, const void* grad_out,

@@ -250,7 +250,10 @@ fc_status fc_rx_demodulate(fc_plan* plan, const void* highrate_in, void* subcarr
 /*
  * Exact adjoint of fc_tx_synthesize (used for gradients): highrate_in ->
  * lowrate_out in the FC_OP_TX low-rate layout, so that
- * <tx(x), y> = <x, adjoint(y)> for the plan's current weights.
+ * <tx(x), y> = <x, adjoint(y)> for the plan's current weights (the RX block
+ * operators with the OLA / OLS roles swapped, Sec. IV). Every lowrate_out
+ * sample is written. Not provided for plans with an FC_SYNC_OLS subband
+ * (FC_E_STATE). Asynchronous on `stream`; errors as fc_rx_analyze.
  */
 fc_status fc_tx_adjoint(fc_plan* plan, const void* highrate_in, void* lowrate_out, void* stream);
 

@@ -190,6 +190,12 @@ EDGE = {
     "narrow_4096": [W.subband(15, 2, 12, 2, 16, 4096, -1500, "sync_ola")],
     # no active subcarriers: only the transition bins carry weight
     "no_active": [tiny("sync_ola", K=0, n_tb=4, ncp=[9, 5, 6, 7, 5])],
+    # short FFTs on the whole workgroup in the long IFFT buffer (L >= 256 at
+    # N >= 2048), synchronised and continuous
+    "wg_short_256_2048": [W.subband(15, 3, 200, 8, 256, 2048, -500, "sync_ola")],
+    "wg_short_512_4096": [W.subband(30, 2, 456, 8, 512, 4096, 900, "sync_ola")],
+    "wg_short_1024_4096_cont": [dict(W.subband(15, 2, 900, 8, 1024, 4096, -1000, "cont_ols"),
+                                     ncp_high=[320, 288])],
 }
 
 

@@ -41,9 +41,20 @@ def test_wideband_oob_continuous_below_synchronised(wide):
 
 def test_wideband_evm_same_for_all_chains(wide):
     S, y, rep = wide
-    e = list(rep["evm_db"].values())
+    e = [v for k, v in rep["evm_db"].items() if "mid-CP" not in k]
+    assert len(e) == 4
     assert max(e) - min(e) < 1.0
     assert max(e) < -30.0
+
+
+def test_wideband_mid_cp_window(wide):
+    """The filters' leakage past the symbol edges falls on the CP ends: a
+    window starting half-way into the CP (phase-compensated) sees less of it
+    than the window after the full CP."""
+    S, y, rep = wide
+    ev = rep["evm_db"]
+    for tx in ("cont_tx", "sync_tx"):
+        assert ev[tx + "/cont_rx mid-CP"] < ev[tx + "/cont_rx"] - 5.0
 
 
 def test_wideband_evm_is_the_filters(wide):

@@ -7,7 +7,8 @@ configurations: continuous OLS TX or synchronised OLA TX, followed by
 continuous OLS RX (then CP removal and the OFDM FFT) or the synchronised RX
 with OFDM demodulation. Reported per chain: the EVM of the active
 subcarriers against the transmitted 64-QAM symbols (FFT window after the
-full CP, the window the synchronised receiver uses); per TX scheme: the
+full CP, the window the synchronised receiver uses; for the continuous
+receiver also a window starting half-way into the CP); per TX scheme: the
 out-of-band power ratio of the Welch PSD. No noise is added, so the EVM is
 the filtering's own distortion.
 
@@ -53,12 +54,19 @@ class Setup:
         out[self.d:self.d + n] = y[:n]
         return out
 
-    def evm_lowrate(self, xh):
+    def evm_lowrate(self, xh, mid_cp=False):
         """Continuous RX output (low-rate CP-OFDM stream) -> EVM of the
-        active subcarriers, window after the full CP."""
+        active subcarriers. Window after the full CP, or (mid_cp) starting
+        half-way into the CP with the linear phase of that advance removed
+        (a window advanced by d samples sees subcarrier k turned by
+        exp(-j 2 pi k d / L))."""
         syms = ofc.split_symbols(xh, self.L, self.pc["lcp"])
-        sc = metrics.ofdm_demod(np.stack([s[len(s) - self.L:] for s in syms]))
-        return metrics.err_db(sc[:, self.act], self.grid)
+        rows = []
+        for sym, lc in zip(syms, self.pc["lcp"]):
+            o = lc // 2 if mid_cp else lc
+            X = metrics.ofdm_demod(sym[o:o + self.L])[0]
+            rows.append(X * np.exp(2j * np.pi * np.arange(self.L) * (lc - o) / self.L))
+        return metrics.err_db(np.stack(rows)[:, self.act], self.grid)
 
     def evm_subcarriers(self, sc):
         return metrics.err_db(np.asarray(sc).reshape(-1, self.L)[:, self.act], self.grid)
@@ -72,10 +80,13 @@ def oracle_chains(S):
     L, N, D = S.L, S.N, S.D
     y = {"cont": ofc.tx_cont(S.x, L, N, 0, D, ola=False),
          "sync": ofc.tx_sync(S.x, L, N, 0, D, S.ps["ncp"])}
-    rx_cont = lambda yh: S.evm_lowrate(ofc.rx_cont(yh, L, N, 0, D, S.pc["n_in"], ola=False))
+    xc = {k: ofc.rx_cont(v, L, N, 0, D, S.pc["n_in"], ola=False)
+          for k, v in (("cont", y["cont"]), ("sync", S.to_cont(y["sync"])))}
     rx_sync = lambda yh: S.evm_subcarriers(ofc.rx_sync_subcarriers(yh, L, N, 0, D, S.ps["ncp"]))
-    evm = {"cont_tx/cont_rx": rx_cont(y["cont"]), "cont_tx/sync_rx": rx_sync(S.to_sync(y["cont"])),
-           "sync_tx/cont_rx": rx_cont(S.to_cont(y["sync"])), "sync_tx/sync_rx": rx_sync(y["sync"])}
+    evm = {"cont_tx/cont_rx": S.evm_lowrate(xc["cont"]), "cont_tx/sync_rx": rx_sync(S.to_sync(y["cont"])),
+           "sync_tx/cont_rx": S.evm_lowrate(xc["sync"]), "sync_tx/sync_rx": rx_sync(y["sync"]),
+           "cont_tx/cont_rx mid-CP": S.evm_lowrate(xc["cont"], True),
+           "sync_tx/cont_rx mid-CP": S.evm_lowrate(xc["sync"], True)}
     oob = {k: S.oob(v) for k, v in y.items()}
     return y, dict(evm_db=evm, oob_db=oob)
 
@@ -93,13 +104,16 @@ def gpu_chains(S):
     y = {k: from_device(p.tx(to_device(S.x, "c64")), "c64") for k, p in plans.items()}
 
     def rx_cont(yh):
-        return S.evm_lowrate(from_device(plans["cont"].rx(to_device(yh, "c64")), "c64"))
+        return from_device(plans["cont"].rx(to_device(yh, "c64")), "c64")
 
     def rx_sync(yh):
         return S.evm_subcarriers(from_device(plans["sync"].rx_demod(to_device(yh, "c64")), "c64"))
 
-    evm = {"cont_tx/cont_rx": rx_cont(y["cont"]), "cont_tx/sync_rx": rx_sync(S.to_sync(y["cont"])),
-           "sync_tx/cont_rx": rx_cont(S.to_cont(y["sync"])), "sync_tx/sync_rx": rx_sync(y["sync"])}
+    xc = {"cont": rx_cont(y["cont"]), "sync": rx_cont(S.to_cont(y["sync"]))}
+    evm = {"cont_tx/cont_rx": S.evm_lowrate(xc["cont"]), "cont_tx/sync_rx": rx_sync(S.to_sync(y["cont"])),
+           "sync_tx/cont_rx": S.evm_lowrate(xc["sync"]), "sync_tx/sync_rx": rx_sync(y["sync"]),
+           "cont_tx/cont_rx mid-CP": S.evm_lowrate(xc["cont"], True),
+           "sync_tx/cont_rx mid-CP": S.evm_lowrate(xc["sync"], True)}
     torch.cuda.synchronize()
     oob = {k: S.oob(v) for k, v in y.items()}
     return y, dict(evm_db=evm, oob_db=oob)

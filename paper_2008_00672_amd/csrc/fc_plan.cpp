@@ -1020,7 +1020,7 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
       if ((result = fc_plan_set_tuning(P, op, len, conc)) != FC_OK) break;
       if (conc > 1 && (result = measure_costs(P, op, in, out, st, e0, e1)) != FC_OK) break;
       float t_min = 1e30f;
-      for (int rep = 0; rep < 4 && result == FC_OK; ++rep) {       // one warm-up, three timed calls
+      for (int rep = 0; rep < 7 && result == FC_OK; ++rep) {       // one warm-up, six timed calls
         if (hipEventRecord(e0, st) != hipSuccess) { result = FC_E_DEVICE; break; }
         if ((result = run_op(P, op, in, out, st)) != FC_OK) break;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {

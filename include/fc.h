@@ -312,7 +312,9 @@ fc_status fc_plan_get_tuning(const fc_plan* plan, int32_t op, int32_t* run_len, 
  * call; out is overwritten) for run_len in {0, 8, 16, 32, 64} (TX) or
  * {0, 1, 2, 4, 8, 16} (RX, adjoint; {0, 2, 4, 8, 16} demodulating RX) and
  * conc in {1, 4}, one warm-up and six timed calls each (HIP events on
- * `stream`, minimum kept), then applies the
+ * `stream`, minimum kept; on a stream other than the legacy null stream the
+ * call is captured once as a HIP graph and the replays are timed, so host
+ * launch gaps do not enter the choice), then applies the
  * fastest. With conc > 1 it first times every kernel launch of the op on its
  * own and spreads the launches over the streams longest first by those
  * measured times (kept until the next fc_plan_set_tuning). Synchronous. The

@@ -118,17 +118,22 @@ def test_graph_sees_new_weights():
     g.close()
 
 
-def test_autotune_keeps_results():
+@pytest.mark.parametrize("side_stream", [False, True], ids=["null_stream", "side_stream"])
+def test_autotune_keeps_results(side_stream):
+    # On the null stream the candidates run eagerly; on another stream each is
+    # captured as a graph and replayed. Either way the stream is left usable.
     import torch
     from paper_2008_00672_amd import OP_TX
     sbs, xs, Ds, p = _batched(48)
     x = to_device(_cat(xs), "f16")
     ref = p.tx(x).clone()
     out = p.empty(ref.shape[0])
-    best = p.autotune(OP_TX, x, out)
-    print("autotune TX:", best, flush=True)
+    s = torch.cuda.Stream() if side_stream else None
+    torch.cuda.synchronize()
+    best = p.autotune(OP_TX, x, out, stream=s)
+    print("autotune TX (%s):" % ("side stream" if side_stream else "null stream"), best, flush=True)
     assert best["run_len"] in (0, 8, 16, 32, 64) and best["conc"] in (1, 4) and best["ms"] > 0
     assert p.get_tuning(OP_TX) == dict(run_len=best["run_len"], conc=best["conc"])
-    y = p.tx(x)
+    y = p.tx(x, stream=s)
     torch.cuda.synchronize()
     assert torch.equal(y, ref)

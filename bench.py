@@ -191,18 +191,20 @@ def wgrad_cost(sbs):
     return flops
 
 
-def traffic(op):
-    """HBM bytes per call of op from the committed rocprofv3 counter summary
-    (profiles/traffic_<op>.json), or None when the kernel sources changed
-    since the counters were taken."""
+def traffic(op, run_len):
+    """HBM bytes per call of op at run_len blocks per task from the committed
+    rocprofv3 counter summary (profiles/traffic_<op>.json), or None when the
+    kernel sources changed since the counters were taken or no counters were
+    taken at that run length."""
     from paper_2008_00672_amd.profsum import kernel_hash
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % op)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_hash") != kernel_hash():
+    rec = d.get("by_run_len", {}).get(str(int(run_len)))
+    if d.get("kernel_hash") != kernel_hash() or rec is None:
         return None
-    return round(d["bytes_per_launch"])
+    return round(rec["bytes_per_launch"])
 
 
 # ------------------------------------------------------------ CPU leg ---
@@ -548,7 +550,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
-    roof["traffic"] = traffic(dk)
+    roof["traffic"] = traffic(dk, tune["rx"]["run_len"])
     roof["kernel"] = "fc_rx_kernel<bf16, N=4096> (one launch per RX call)"
     roof["algorithmic_bytes"] = int(d_bytes)
     roof["algorithmic_flops"] = int(d_flops)
@@ -562,7 +564,7 @@ def main():
                        "flops": "executed (long IFFT pruned to the band)",
                        "achieved_tflops_nominal": round(tx_flops_nominal / tx_ms / 1e9, 2),
                        "hbm_gbs": round(tx_bytes / tx_ms / 1e6, 1), "algorithmic_bytes": int(tx_bytes),
-                       "algorithmic_flops": int(tx_flops), "traffic": traffic("fc_tx")}
+                       "algorithmic_flops": int(tx_flops), "traffic": traffic("fc_tx", tune["tx"]["run_len"])}
 
     # ---------------- plain FP32 form ----------------
     plain = None

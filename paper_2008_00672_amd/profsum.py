@@ -2,14 +2,17 @@
 
   python -m paper_2008_00672_amd.profsum stats <kernel_stats.csv> <out.md> "<command>"
   python -m paper_2008_00672_amd.profsum traffic <op> <fetch.csv> <write.csv> \
-         <calib_fetch.csv> <calib_write.csv> <calls> <out.json> "<command>"
+         <calib_fetch.csv> <calib_write.csv> <calls> <out.json> "<command>" <run_len>
 
 `stats` turns a --kernel-trace --stats summary into a short markdown table.
 `traffic` sums FETCH_SIZE / WRITE_SIZE (KiB per dispatch) over the dispatches
 of one operation (all fc_tx_* kernels, or fc_rx_kernel), divides by the number
 of calls, and scales each counter by known-bytes / reading of a plain 256 MiB
-device copy profiled with the same counter. The result records a hash of the
-kernel sources so bench.py can tell whether it is still current.
+device copy profiled with the same counter. The traffic depends on the work
+split (blocks per task: a run re-reads the input its first block overlaps),
+so each record is kept under the run length it was taken at, several per
+file. The file records a hash of the kernel sources so bench.py can tell
+whether it is still current; records of another hash are dropped.
 """
 import csv
 import hashlib
@@ -87,36 +90,46 @@ OPS = {
 }
 
 
-def traffic(op, fetch, write, cfetch, cwrite, calls, out, command):
+def traffic(op, fetch, write, cfetch, cwrite, calls, out, command, run_len):
+    """Add (or replace) the record of op at blocks-per-task run_len in out."""
     sel = OPS[op]
     f_kib, nf = _dispatch_values(fetch, "FETCH_SIZE", sel)
     w_kib, nw = _dispatch_values(write, "WRITE_SIZE", sel)
     ff = COPY_BYTES / (_copy_reading(cfetch, "FETCH_SIZE") * 1024.0)
     fw = COPY_BYTES / (_copy_reading(cwrite, "WRITE_SIZE") * 1024.0)
     per_call = (f_kib * 1024.0 * ff + w_kib * 1024.0 * fw) / calls
-    d = {"op": op, "kernel_hash": kernel_hash(), "bytes_per_launch": per_call,
-         "fetch_kib_per_call": f_kib / calls, "write_kib_per_call": w_kib / calls,
-         "copy_factor_fetch": ff, "copy_factor_write": fw, "dispatches": [nf, nw], "calls": calls,
-         "command": command}
+    h = kernel_hash()
+    d = json.load(open(out)) if os.path.exists(out) else {}
+    if d.get("kernel_hash") != h or "by_run_len" not in d:
+        d = {"op": op, "kernel_hash": h, "by_run_len": {}}
+    d["by_run_len"][str(int(run_len))] = {
+        "bytes_per_launch": per_call, "fetch_kib_per_call": f_kib / calls, "write_kib_per_call": w_kib / calls,
+        "copy_factor_fetch": ff, "copy_factor_write": fw, "dispatches": [nf, nw], "calls": calls,
+        "command": command}
+    d["by_run_len"] = dict(sorted(d["by_run_len"].items(), key=lambda kv: int(kv[0])))
     json.dump(d, open(out, "w"), indent=1)
     return d
 
 
 def traffic_md(jsons, out, commands):
-    """Markdown table of the traffic summaries (one per op)."""
+    """Markdown table of the traffic summaries (one row per op and run length)."""
     ds = [json.load(open(j)) for j in jsons]
+    recs = [(d["op"], int(k), r) for d in ds for k, r in d["by_run_len"].items()]
     lines = ["# HBM traffic per call (rocprofv3 FETCH_SIZE / WRITE_SIZE)", "",
-             "Counter runs (repo root, MI355X), one counter per run:", ""]
+             "Counter runs (repo root, MI355X), one counter per run; `--tuning` fixes the blocks per task "
+             "(tx_run_len,tx_conc,rx_run_len,rx_conc; the grid-input TX and the demodulating RX take the TX "
+             "and RX values):", ""]
     lines += ["    " + c for c in commands]
     lines += ["", "Calibration: a plain 256 MiB device copy under the same counters gives the scale factors "
-                  "FETCH x%.4f, WRITE x%.4f (known bytes / counter reading)." % (ds[0]["copy_factor_fetch"],
-                                                                                  ds[0]["copy_factor_write"]), "",
-              "| op | dispatches per call | FETCH KiB/call | WRITE KiB/call | calibrated HBM bytes/call |",
-              "|---|---|---|---|---|"]
-    for d in ds:
-        lines.append("| %s | %d | %.0f | %.0f | %.4g |" % (d["op"], d["dispatches"][0] // d["calls"],
-                                                          d["fetch_kib_per_call"], d["write_kib_per_call"],
-                                                          d["bytes_per_launch"]))
+                  "FETCH x%.4f, WRITE x%.4f (known bytes / counter reading)." % (recs[0][2]["copy_factor_fetch"],
+                                                                                  recs[0][2]["copy_factor_write"]),
+              "", "| op | blocks per task | dispatches per call | FETCH KiB/call | WRITE KiB/call | "
+                  "calibrated HBM bytes/call |",
+              "|---|---|---|---|---|---|"]
+    for op, k, r in recs:
+        lines.append("| %s | %d | %d | %.0f | %.0f | %.4g |" % (op, k, r["dispatches"][0] // r["calls"],
+                                                               r["fetch_kib_per_call"], r["write_kib_per_call"],
+                                                               r["bytes_per_launch"]))
     lines += ["", "Kernel source hash: %s (code lines, comments excluded)" % ds[0]["kernel_hash"], ""]
     open(out, "w").write("\n".join(lines))
 
@@ -127,4 +140,4 @@ if __name__ == "__main__":
     elif sys.argv[1] == "traffic_md":
         traffic_md(sys.argv[2].split(","), sys.argv[3], sys.argv[4:])
     elif sys.argv[1] == "traffic":
-        print(traffic(sys.argv[2], *sys.argv[3:7], int(sys.argv[7]), sys.argv[8], sys.argv[9]))
+        print(traffic(sys.argv[2], *sys.argv[3:7], int(sys.argv[7]), sys.argv[8], sys.argv[9], int(sys.argv[10])))

@@ -723,7 +723,7 @@ __global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void
   const int rtid = (tid + 64 * (int)(blockIdx.x & 3)) & (kThreads - 1);
   const int sid = kWaveShort ? tid & 63 : tid;          // index within the short FFT's threads
   constexpr int NTS = kWaveShort ? 64 : kThreads;
-  constexpr int RMS = kWaveShort ? 16 : radix_cap(L);      // short-FFT radix plan (all threads busy)
+  constexpr int RMS = kWaveShort ? wave_radix_cap(L) : radix_cap(L);   // short-FFT radix plan
   float2* band = kWaveShort ? bands + wave * lds_elems(L) : buf;
   int64_t prev_end = INT64_MIN;
   LoadAhead<IO, NTS, L, RMS> ld;
@@ -913,7 +913,7 @@ __global__ __launch_bounds__(kThreads, 4) void fc_rx_kernel(LaunchArgs a, int) {
           so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
           LoadCompact<64, LL> lc2;
           lc2.R = S + Sb.cofs; lc2.D = a.weights + Sb.w_off; lc2.ph = make_float2(Z.ph.x, Z.ph.y);
-          fft_run<64, LL, 0, +1>(S + Sb.cofs, lane, lc2, so, tw);
+          fft_run<64, LL, 0, +1, wave_radix_cap(LL)>(S + Sb.cofs, lane, lc2, so, tw);
         }
       }
     };
@@ -951,14 +951,14 @@ __device__ __forceinline__ float2 rot_j(float2 v, int k) {
 
 // First pass of the per-symbol IFFT: V[u] = A[u] - B[u], A from the first
 // block (stored), B[u] = g1[u] (-j)^u from the second block's region.
-template <int NT, int L> struct LoadV {
+template <int NT, int L, int RM> struct LoadV {
   const float2* A; const float2* R; const float* D; float2 ph;
   float d[16];
   __device__ __forceinline__ void prefetch(int tid) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       int u, b;
-      if (first_pos<NT, L, 0>(s, tid, u, b)) d[s] = D[(u + (L >> 1)) & (L - 1)];
+      if (first_pos<NT, L, 0, RM>(s, tid, u, b)) d[s] = D[(u + (L >> 1)) & (L - 1)];
     }
   }
   __device__ __forceinline__ float2 operator()(int slot, int u, int, int up) const {
@@ -984,13 +984,13 @@ struct LoadPadded : NoPrefetch {
 
 // Last pass of that FFT: x[u] = (C V)[u] + B[u], scaled by 1/sqrt(L), to the
 // symbol's subcarrier u.
-template <int IO, int NT, int L> struct StoreSubcarriers {
+template <int IO, int NT, int L, int RM> struct StoreSubcarriers {
   const float2* R; const float* D; float2 ph; typename Io<IO>::T* out; float scale;
   float d[16];
   __device__ __forceinline__ void prefetch(int tid) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int u = last_pos<NT, L, 0>(s, tid);
+      const int u = last_pos<NT, L, 0, RM>(s, tid);
       if (u >= 0) d[s] = D[(u + (L >> 1)) & (L - 1)];
     }
   }
@@ -1070,18 +1070,19 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
           const BlockSb Z = a.bsb[B1.bs + m];
           const float2 ph = make_float2(Z.ph.x, Z.ph.y);
           float2* A = Ab + Sb.cofs;
-          LoadV<64, LL> lv;
+          constexpr int RMW = wave_radix_cap(LL);
+          LoadV<64, LL, RMW> lv;
           lv.A = A; lv.R = S + Sb.cofs; lv.D = a.weights + Sb.w_off; lv.ph = ph;
           StoreMask sm;
           sm.A = A; sm.half = LL / 2; sm.inv_l = 1.f / LL;
-          fft_run<64, LL, 0, +1>(A, lane, lv, sm, tw);
+          fft_run<64, LL, 0, +1, RMW>(A, lane, lv, sm, tw);
           wave_sync();
           LoadPadded lp;
           lp.A = A;
-          StoreSubcarriers<IO, 64, LL> so;
+          StoreSubcarriers<IO, 64, LL, RMW> so;
           so.R = S + Sb.cofs; so.D = a.weights + Sb.w_off; so.ph = ph; so.out = at<IO>(a.out, Z.x0);
           so.scale = rsqrtf((float)LL);
-          fft_run<64, LL, 0, -1>(A, lane, lp, so, tw);
+          fft_run<64, LL, 0, -1, RMW>(A, lane, lp, so, tw);
         }
       }
     };
@@ -1096,19 +1097,20 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
           const BlockSb Z = a.bsb[B1.bs + m];
           const float2 ph = make_float2(Z.ph.x, Z.ph.y);
           float2* A = Ab + Sb.cofs;
-          LoadV<kThreads, LL> lv;
+          constexpr int RMG = radix_cap(LL);
+          LoadV<kThreads, LL, RMG> lv;
           lv.A = A; lv.R = S + Sb.cofs; lv.D = a.weights + Sb.w_off; lv.ph = ph;
           StoreMask sm;
           sm.A = A; sm.half = LL / 2; sm.inv_l = 1.f / LL;
           __syncthreads();
-          fft_run<kThreads, LL, 0, +1>(A, tid, lv, sm, tw);
+          fft_run<kThreads, LL, 0, +1, RMG>(A, tid, lv, sm, tw);
           __syncthreads();
           LoadPadded lp;
           lp.A = A;
-          StoreSubcarriers<IO, kThreads, LL> so;
+          StoreSubcarriers<IO, kThreads, LL, RMG> so;
           so.R = S + Sb.cofs; so.D = a.weights + Sb.w_off; so.ph = ph; so.out = at<IO>(a.out, Z.x0);
           so.scale = rsqrtf((float)LL);
-          fft_run<kThreads, LL, 0, -1>(A, tid, lp, so, tw);
+          fft_run<kThreads, LL, 0, -1, RMG>(A, tid, lp, so, tw);
         }
       }
     };
@@ -1183,7 +1185,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
         auto issue = [&](auto lc) {
           constexpr int LL = decltype(lc)::value;
           if constexpr (LL <= NL) {
-            if (L == LL) lx.template issue_sized<LL>(at<IO>(a.in2, Z.x0), Z.lo, Z.hi, lane);
+            if (L == LL) lx.template issue_sized<LL, wave_radix_cap(LL)>(at<IO>(a.in2, Z.x0), Z.lo, Z.hi, lane);
           }
         };
         issue(SizeC<1024>()); issue(SizeC<512>()); issue(SizeC<256>()); issue(SizeC<128>());
@@ -1208,7 +1210,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
             if (L != LL) return;
             StoreGrad sg;
             sg.R = reg + wave * le; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = gacc + wave * L;
-            fft_run<64, LL, 0, -1>(sbuf + wave * le, lane, lx, sg, tw);
+            fft_run<64, LL, 0, -1, wave_radix_cap(LL)>(sbuf + wave * le, lane, lx, sg, tw);
           }
         };
         run(SizeC<1024>()); run(SizeC<512>()); run(SizeC<256>()); run(SizeC<128>());
@@ -1262,7 +1264,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
           StoreGrad sg;
           sg.R = S + Sb.cofs; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = acc + Sb.aofs;
           wave_sync();
-          fft_run<64, LL, 0, -1>(scr + wave * G.wstride, lane, ls, sg, tw);
+          fft_run<64, LL, 0, -1, wave_radix_cap(LL)>(scr + wave * G.wstride, lane, ls, sg, tw);
         }
       }
     };

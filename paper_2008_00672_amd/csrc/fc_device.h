@@ -866,9 +866,12 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
 // spectrum); then each subband's short IFFT runs in place in its region:
 // subbands with L <= 1024 as one-wave transforms on the wave the planner
 // chose, longer ones on the whole workgroup. The next block's input is
-// loaded into registers while the subbands run.
+// loaded into registers while the subbands run. Registers are bounded for
+// four waves per SIMD (what the LDS allows at N = 4096); FP32 storage holds
+// twice the prefetched input and would spill there (40 registers, 10 %
+// slower than three waves without spills), so it takes three.
 template <int IO, int NL>
-__global__ __launch_bounds__(kThreads, 4) void fc_rx_kernel(LaunchArgs a, int) {
+__global__ __launch_bounds__(kThreads, IO == IO_C64 ? 3 : 4) void fc_rx_kernel(LaunchArgs a, int) {
   extern __shared__ float2 smem[];
   // consecutive tasks (runs sharing input at their boundary) go to the same
   // XCD: the dispatcher places workgroup i on XCD i mod 8

@@ -193,6 +193,28 @@ def test_tuning_host_plan():
             p.set_tuning(fc.OP_TX, **dict(dict(run_len=0, conc=4), **bad))
 
 
+def test_autotune_host_plan_rejected():
+    """The autotuner needs a device plan: a host-only plan gets FC_E_STATE and
+    missing buffers or an unknown op FC_E_ARG, before any device call; the
+    result pointers and the tuning are left alone."""
+    import ctypes
+    fc = _lib()
+    E_ARG, E_STATE = -1, -6                    # fc_status values of include/fc.h
+    sbs, _ = W.mixed_numerology()
+    p = _plan(sbs)
+    L = fc.lib()
+    r, c, ms = ctypes.c_int32(-7), ctypes.c_int32(-7), ctypes.c_float(-1.0)
+    dummy = ctypes.c_void_p(16)                # never dereferenced: the calls fail first
+    out = (ctypes.byref(r), ctypes.byref(c), ctypes.byref(ms))
+    assert L.fc_plan_autotune(p._h, fc.OP_TX, dummy, dummy, None, *out) == E_STATE
+    assert L.fc_plan_autotune(p._h, fc.OP_TX, None, dummy, None, *out) == E_ARG
+    assert L.fc_plan_autotune(p._h, fc.OP_TX, dummy, None, None, *out) == E_ARG
+    assert L.fc_plan_autotune(p._h, 7, dummy, dummy, None, *out) == E_ARG
+    assert L.fc_plan_autotune(None, fc.OP_TX, dummy, dummy, None, *out) == E_ARG
+    assert (r.value, c.value, ms.value) == (-7, -7, -1.0)
+    assert p.get_tuning(fc.OP_TX) == dict(run_len=0, conc=4)
+
+
 def test_rx_demod_layout_and_validity():
     """The demodulating RX has the synchronised RX layout (L values per symbol)
     and needs synchronised subbands."""

@@ -118,9 +118,9 @@ constexpr int twb_total() { return twb_plan_total(16) + twb_plan_total(8) + twb_
 // largest radix for interleaved transforms of N points in all on 256 threads
 constexpr int radix_cap(int N) { return N >= 4096 ? 16 : (N >= 2048 ? 8 : 4); }
 // the same for one P-point transform on one wave (64 threads): radix 16 for
-// 1024 points, 8 for 512, 4 below, so that at least a quarter of the lanes
-// (all of them from 256 points up) hold a butterfly in every pass instead of
-// 16 lanes running the 256-point transform's two radix-16 passes
+// 1024 points, 8 for 512, 4 below, so that from 256 points up every lane
+// holds a butterfly in every pass (radix-16 passes left 48 of the 64 lanes
+// idle at 256 points) and below it the fewest lanes idle that radix 4 allows
 constexpr int wave_radix_cap(int P) { return P >= 1024 ? 16 : (P >= 512 ? 8 : 4); }
 
 // One subband, shared by all operations.

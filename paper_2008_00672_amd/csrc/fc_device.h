@@ -1138,6 +1138,21 @@ struct StoreGrad : NoPrefetch {
   }
 };
 
+// The same with each thread's sums in registers: output slot s of the last
+// pass is bin last_pos(s) in every block, so the thread that produces a bin
+// is the one that accumulates it.
+struct StoreGradReg : NoPrefetch {
+  const float2* R; float2 ph; float r[16];
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) r[s] = 0.f;
+  }
+  __device__ __forceinline__ void operator()(int slot, int, float2 x, int up) {
+    const float2 a = cmul(R[up], ph);
+    r[slot] += a.x * x.x + a.y * x.y;
+  }
+};
+
 // Per block, as the adjoint: long FFT of the gradient block scattered into
 // the subband regions; then per subband the short FFT of the forward input
 // block (window and phase of the forward transform) in a scratch buffer,
@@ -1229,23 +1244,50 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
     }
     return;
   }
+  if (G.n_sb == 1 && G.n_long_sb == 1) {
+    // one subband with a whole-workgroup short FFT (L > 1024): its forward
+    // input block is loaded while the block's long FFT runs, and every thread
+    // keeps the sums of its own bins in registers (these groups have launches
+    // of their own, without the LDS accumulators)
+    const SbDesc Sb = a.sb[G.sb_first];
+    auto run = [&](auto lc) {
+      constexpr int LL = decltype(lc)::value;
+      if constexpr (LL <= NL && LL > 1024) {
+        if (Sb.L != LL) return;
+        constexpr int RML = radix_cap(LL);
+        StoreGradReg sg;
+        sg.clear();
+        LoadAhead<IO, kThreads, LL, RML> lx;
+        for (int bi = 0; bi < T.blk_count; ++bi) {
+          const BlockDesc B = a.blk[T.blk_first + bi];
+          const BlockSb Z = a.bsb[B.bs];
+          lx.issue(at<IO>(a.in2, Z.x0), Z.lo, Z.hi, tid);
+          StoreScatter sc;
+          sc.S = S; sc.map = map;
+          __syncthreads();
+          fft_run<kThreads, NL, 0, -1, radix_cap(NL)>(S, tid, lh, sc, tw);
+          if (bi + 1 < T.blk_count) {
+            const BlockDesc Bn = a.blk[T.blk_first + bi + 1];
+            lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
+          }
+          __syncthreads();
+          sg.R = S + Sb.cofs; sg.ph = make_float2(Z.ph.x, Z.ph.y);
+          fft_run<kThreads, LL, 0, -1, RML>(scr, tid, lx, sg, tw);
+        }
+        float* gw = reinterpret_cast<float*>(a.out);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          const int u = last_pos<kThreads, LL, 0, RML>(s, tid);
+          if (u >= 0) atomicAdd(gw + Sb.w_off + ((u + (LL >> 1)) & (LL - 1)), sg.r[s]);
+        }
+      }
+    };
+    run(SizeC<2048>()); run(SizeC<4096>());
+    return;
+  }
   for (int i = tid; i < G.acc_len; i += kThreads) acc[i] = 0.f;
-  // one subband with a whole-workgroup short FFT (L > 1024): its forward
-  // input block is loaded while the block's long FFT runs
-  const bool xpre = G.n_sb == 1 && G.n_long_sb == 1;
-  LoadAhead<IO, kThreads, 4096> lxl;
   for (int bi = 0; bi < T.blk_count; ++bi) {
     const BlockDesc B = a.blk[T.blk_first + bi];
-    if (xpre) {
-      const BlockSb Z = a.bsb[B.bs];
-      const int L1 = a.sb[G.sb_first].L;
-      if constexpr (NL >= 2048) {
-        if (L1 == 2048) lxl.template issue_sized<2048, radix_cap(2048)>(at<IO>(a.in2, Z.x0), Z.lo, Z.hi, tid);
-      }
-      if constexpr (NL >= 4096) {
-        if (L1 == 4096) lxl.template issue_sized<4096, radix_cap(4096)>(at<IO>(a.in2, Z.x0), Z.lo, Z.hi, tid);
-      }
-    }
     StoreScatter sc;
     sc.S = S; sc.map = map;
     __syncthreads();
@@ -1283,13 +1325,9 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
           StoreGrad sg;
           sg.R = S + Sb.cofs; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = acc + Sb.aofs;
           __syncthreads();
-          if (xpre) {
-            fft_run<kThreads, LL, 0, -1, radix_cap(LL)>(scr, tid, lxl, sg, tw);
-          } else {
-            LoadSeg<IO> ls;
-            ls.x = at<IO>(a.in2, Z.x0); ls.lo = Z.lo; ls.hi = Z.hi;
-            fft_run<kThreads, LL, 0, -1, radix_cap(LL)>(scr, tid, ls, sg, tw);
-          }
+          LoadSeg<IO> ls;
+          ls.x = at<IO>(a.in2, Z.x0); ls.lo = Z.lo; ls.hi = Z.hi;
+          fft_run<kThreads, LL, 0, -1, radix_cap(LL)>(scr, tid, ls, sg, tw);
         }
       }
     };

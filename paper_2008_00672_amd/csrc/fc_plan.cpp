@@ -530,14 +530,19 @@ void build_op(fc_plan* P, int kind) {
         t.group = (int)g; t.blk_first = first_blk + b; t.blk_count = std::min(K, nblk - b);
         t.accumulate = acc ? 1 : 0;
         PhaseTasks& ph = acc ? ((b & 1) ? rx_odd : rx_even) : rx_all;
-        ClassTasks& ct = ph.cls[std::make_tuple(kind == 3 ? 4 : 2, N, 0)];
+        const GroupDesc& gd = op.grp[g];
+        // adjoint: one-subband groups with a whole-workgroup short transform
+        // get launches of their own, whose weight gradient keeps its sums in
+        // registers (no LDS accumulators: one more workgroup per CU)
+        const bool greg = kind == 2 && gd.n_sb == 1 && gd.n_long_sb == 1;
+        ClassTasks& ct = ph.cls[std::make_tuple(kind == 3 ? 4 : 2, N, greg ? 1 : 0)];
         ct.t.push_back(t);
         // demodulating RX: a second set of subband regions holds the first
         // block's spectra while the second block's long FFT runs
         ct.lds = std::max(ct.lds, (size_t)(std::max(lds_elems(N), lsum) + (kind == 3 ? lsum : 0)) * 8);
-        const GroupDesc& gd = op.grp[g];
         ct.glds = std::max(ct.glds, gd.wg_nb ? (size_t)wgg_lds_entries(lmax, N, gd.wg_nb) * 8
-                                              : (size_t)(gd.acc_off + (gd.acc_len + 1) / 2) * 8);
+                                    : greg   ? (size_t)gd.acc_off * 8
+                                             : (size_t)(gd.acc_off + (gd.acc_len + 1) / 2) * 8);
       }
     }
   }

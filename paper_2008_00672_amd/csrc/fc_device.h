@@ -1186,13 +1186,15 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
   if (G.wg_nb > 0) {
     // one subband, L <= 1024: the long FFTs of a group of blocks scatter into
     // one band region each, then every wave runs the short FFT of one
-    // block's forward input against its region, with its own accumulators
+    // block's forward input against its region. Each lane keeps the sums of
+    // its own bins in registers (the same bins in every block); at the end
+    // the waves' sums meet in LDS.
     const SbDesc Sb = a.sb[G.sb_first];
     const int L = Sb.L, NBG = G.wg_nb, le = lds_elems(L);
     float2* reg = S + lds_elems(NL);
     float2* sbuf = reg + NBG * le;
-    float* gacc = reinterpret_cast<float*>(sbuf + NBG * le);
-    for (int i = tid; i < NBG * L; i += kThreads) gacc[i] = 0.f;
+    StoreGradReg sg;
+    sg.clear();
     // this wave's forward-input block of the group, loaded while the group's
     // long FFTs run
     LoadAhead<IO, 64, 1024> lx;
@@ -1226,8 +1228,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
           constexpr int LL = decltype(lc)::value;
           if constexpr (LL <= NL) {
             if (L != LL) return;
-            StoreGrad sg;
-            sg.R = reg + wave * le; sg.ph = make_float2(Z.ph.x, Z.ph.y); sg.acc = gacc + wave * L;
+            sg.R = reg + wave * le; sg.ph = make_float2(Z.ph.x, Z.ph.y);
             fft_run<64, LL, 0, -1, wave_radix_cap(LL)>(sbuf + wave * le, lane, lx, sg, tw);
           }
         };
@@ -1236,10 +1237,29 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
       }
     }
     __syncthreads();
+    // the long-FFT buffer and the band regions after it are free now and
+    // hold the NBG waves' sums (NBG L floats = NBG L / 2 complex entries)
+    float* red = reinterpret_cast<float*>(S);
+    if (wave < NBG) {
+      auto put = [&](auto lc) {
+        constexpr int LL = decltype(lc)::value;
+        if constexpr (LL <= NL) {
+          if (L != LL) return;
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            const int u = last_pos<64, LL, 0, wave_radix_cap(LL)>(s, lane);
+            if (u >= 0) red[wave * LL + u] = sg.r[s];
+          }
+        }
+      };
+      put(SizeC<1024>()); put(SizeC<512>()); put(SizeC<256>()); put(SizeC<128>());
+      put(SizeC<64>()); put(SizeC<32>()); put(SizeC<16>());
+    }
+    __syncthreads();
     float* gw = reinterpret_cast<float*>(a.out);
     for (int u = tid; u < L; u += kThreads) {
       float sum = 0.f;
-      for (int w = 0; w < NBG; ++w) sum += gacc[w * L + u];
+      for (int w = 0; w < NBG; ++w) sum += red[w * L + u];
       atomicAdd(gw + Sb.w_off + ((u + (L >> 1)) & (L - 1)), sum);
     }
     return;

@@ -47,10 +47,10 @@ constexpr int pruned_waves_per_simd(int L, int N) {
 }
 
 // Weight gradient of a one-subband group with L <= 1024, blocks in groups:
-// long-FFT buffer, then per block of a group its band region, its short-FFT
-// buffer and L float accumulators; the most of {4, 2, 1} blocks within
-// 80 KiB (two workgroups per CU).
-constexpr int wgg_lds_entries(int L, int N, int nb) { return lds_elems(N) + 2 * nb * lds_elems(L) + nb * L / 2; }
+// long-FFT buffer, then per block of a group its band region and its
+// short-FFT buffer (the per-bin sums are held in registers); the most of
+// {4, 2, 1} blocks within 80 KiB (at least two workgroups per CU).
+constexpr int wgg_lds_entries(int L, int N, int nb) { return lds_elems(N) + 2 * nb * lds_elems(L); }
 constexpr int wgg_group_blocks(int L, int N) {
   return wgg_lds_entries(L, N, 4) * 8 <= 80 * 1024 ? 4 : wgg_lds_entries(L, N, 2) * 8 <= 80 * 1024 ? 2 : 1;
 }

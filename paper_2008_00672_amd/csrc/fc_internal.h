@@ -49,10 +49,14 @@ constexpr int pruned_waves_per_simd(int L, int N) {
 // Weight gradient of a one-subband group with L <= 1024, blocks in groups:
 // long-FFT buffer, then per block of a group its band region and its
 // short-FFT buffer (the per-bin sums are held in registers); the most of
-// {4, 2, 1} blocks within 80 KiB (at least two workgroups per CU).
+// {4, 2, 1} blocks that lets three workgroups share a CU, else the most
+// within 80 KiB (two workgroups).
 constexpr int wgg_lds_entries(int L, int N, int nb) { return lds_elems(N) + 2 * nb * lds_elems(L); }
 constexpr int wgg_group_blocks(int L, int N) {
-  return wgg_lds_entries(L, N, 4) * 8 <= 80 * 1024 ? 4 : wgg_lds_entries(L, N, 2) * 8 <= 80 * 1024 ? 2 : 1;
+  return wgg_lds_entries(L, N, 4) * 8 <= 163840 / 3 ? 4
+         : wgg_lds_entries(L, N, 2) * 8 <= 163840 / 3 ? 2
+         : wgg_lds_entries(L, N, 1) * 8 <= 163840 / 3 ? 1
+         : wgg_lds_entries(L, N, 4) * 8 <= 80 * 1024 ? 4 : wgg_lds_entries(L, N, 2) * 8 <= 80 * 1024 ? 2 : 1;
 }
 
 struct Cf {   // complex float with the same layout as HIP's float2

@@ -1156,9 +1156,10 @@ struct StoreGradReg : NoPrefetch {
 // Per block, as the adjoint: long FFT of the gradient block scattered into
 // the subband regions; then per subband the short FFT of the forward input
 // block (window and phase of the forward transform) in a scratch buffer,
-// whose last pass accumulates the products. Each accumulator belongs to one
-// thread for the whole task; at the end the task adds its sums into grad_w
-// (float atomics: tasks of one subband run concurrently).
+// whose last pass accumulates the products. Each sum belongs to one thread
+// for the whole task (in registers for one-subband groups, in LDS for groups
+// of several subbands); at the end the task adds its sums into grad_w (float
+// atomics: tasks of one subband run concurrently).
 template <int IO, int NL>
 __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
   extern __shared__ float2 smem[];

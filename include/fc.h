@@ -185,9 +185,15 @@ fc_status fc_plan_symbols(const fc_plan* plan, int32_t sb, int32_t* ncp_high, in
 fc_status fc_set_weights(fc_plan* plan, int32_t sb, const float* w_host, int32_t n, void* stream);
 
 /*
- * Same as fc_set_weights with a device pointer w_dev (n == n_short floats):
- * an asynchronous device-to-device copy on `stream`; the host is not
- * synchronised and fc_get_weights reads the device copy.
+ * Same as fc_set_weights with a device pointer w_dev: an asynchronous
+ * device-to-device copy on `stream`; the host is not synchronised and
+ * fc_get_weights reads the device copy. sb >= 0: n == that subband's
+ * n_short floats; sb == -1: every subband's weights at once, concatenated in
+ * plan order (n == sum_m n_short_m, the layout of fc_tx_weight_grad's
+ * grad_w). The values are not read on the host and NOT checked for
+ * finiteness: the caller must pass finite weights (a NaN or Inf reaches
+ * every output sample of its subband and grad_w). Errors: FC_E_ARG,
+ * FC_E_SHAPE, FC_E_STATE (host-only plan), FC_E_DEVICE.
  */
 fc_status fc_set_weights_device(fc_plan* plan, int32_t sb, const float* w_dev, int32_t n, void* stream);
 

@@ -4,6 +4,11 @@ approximates linear convolution through block-wise circular convolutions).
 
 Test infrastructure only (see ``oracle/__init__``).
 
+Pinned (tests/lin_metric_pins.py): textbook convolution at I = 1 (continuous
+and per symbol), the steady-state tone response at I > 1, the synchronised
+form as a sum of shifted single-symbol continuous forms, and both receivers
+as exact adjoints of their transmitters.
+
 The FC block with real weights D, centre bin c and interpolation I applies, in
 its own time axis, y[tau] = sqrt(I) exp(j2pi c tau/N) sum_i s[i] g0[(tau - I i) mod N]
 with the N-periodic kernel g0[d] = (1/N) sum_p D[p] exp(j2pi (p - L/2) d / N).

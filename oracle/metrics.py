@@ -1,6 +1,11 @@
 """OFDM demodulation, error and leakage metrics, complexity formula (oracle).
 
 Test infrastructure only (see ``oracle/__init__``).
+
+Pinned (tests/lin_metric_pins.py): the window by its closed-form values and
+scipy's periodic Blackman-Harris window, the PSD by scipy's Welch estimate,
+the out-of-band ratio by tones whose seven-line spectra give closed forms at
+the in-band region's edges, the complexity formula by hand-evaluated cases.
 """
 import numpy as np
 

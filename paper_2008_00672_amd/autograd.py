@@ -14,11 +14,7 @@ from .fc import OP_TX
 
 
 def _set_all(plan, w):
-    off = 0
-    for i, s in enumerate(plan.subbands):
-        L = s["n_short"]
-        plan.set_weights(i, w[off:off + L])
-        off += L
+    plan.set_all_weights(w)
 
 
 class FcTx(torch.autograd.Function):

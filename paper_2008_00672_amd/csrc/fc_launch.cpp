@@ -1,6 +1,8 @@
 // Launch dispatch over the I/O storage types (host code).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fc_internal.h"
 
 namespace fcx {
@@ -34,9 +36,23 @@ hipError_t launch_zero(void* out, int64_t n, int io, hipStream_t s) {
   }
 }
 
+// The dynamic-LDS limit is a property of each kernel function, shared by
+// every plan in the process: it is only ever raised (per device, under a
+// lock), so a plan that needs less never lowers the limit for the launches
+// of a plan that needs more.
 hipError_t set_lds_limits(size_t bytes) {
+  static std::mutex mu;
+  static size_t granted[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (bytes <= granted[dev]) return hipSuccess;
   hipError_t a = lds_limits_io0(bytes), b = lds_limits_io1(bytes), c = lds_limits_io2(bytes);
-  return a != hipSuccess ? a : (b != hipSuccess ? b : c);
+  e = a != hipSuccess ? a : (b != hipSuccess ? b : c);
+  if (e == hipSuccess) granted[dev] = bytes;
+  return e;
 }
 
 }  // namespace fcx

@@ -742,12 +742,24 @@ fc_status measure_costs(fc_plan* P, int kind, const void* in, void* out, hipStre
   return FC_OK;
 }
 
+// Dynamic LDS beyond 64 KiB must be granted per kernel function before the
+// plan's launches (the grant is process-wide and only ever raised).
+fc_status grant_lds(const fc_plan* P) {
+  size_t lds_max = 0;
+  for (int k = 0; k < 5; ++k)
+    for (const auto& ph : P->op[k].phases) lds_max = std::max(lds_max, std::max(ph.lds, ph.glds));
+  if (lds_max > 65536 && set_lds_limits(lds_max) != hipSuccess) return FC_E_UNSUPPORTED;
+  return FC_OK;
+}
+
 // Rebuild one op's tables with the plan's current tuning (device work on the
 // old tables must have finished).
 fc_status rebuild_op(fc_plan* P, int kind) {
   if (P->device >= 0) free_op(P->op[kind]);
   build_op(P, kind);
-  return P->device >= 0 ? upload_op(P->op[kind]) : FC_OK;
+  if (P->device < 0) return FC_OK;
+  const fc_status st = upload_op(P->op[kind]);
+  return st ? st : grant_lds(P);
 }
 
 }  // namespace
@@ -869,10 +881,7 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   if (!st) st = upload(twp, &P->d_twp);
   if (!st) st = upload(w, &P->d_w);
   for (int k = 0; k < 5 && !st; ++k) st = upload_op(P->op[k]);
-  size_t lds_max = 0;
-  for (int k = 0; k < 5; ++k)
-    for (auto& ph : P->op[k].phases) lds_max = std::max(lds_max, std::max(ph.lds, ph.glds));
-  if (!st && lds_max > 65536 && set_lds_limits(lds_max) != hipSuccess) st = FC_E_UNSUPPORTED;
+  if (!st) st = grant_lds(P);
   // side streams (default priority) and fork/join events
   for (int q = 0; q + 1 < kMaxConc && !st; ++q) {
     if (hipStreamCreateWithFlags(&P->side[q], hipStreamNonBlocking) != hipSuccess) { P->side[q] = nullptr; st = FC_E_DEVICE; }
@@ -949,15 +958,15 @@ fc_status fc_set_weights(fc_plan* P, int32_t sb, const float* w_host, int32_t n,
 }
 
 fc_status fc_set_weights_device(fc_plan* P, int32_t sb, const float* w_dev, int32_t n, void* stream) {
-  if (!P || !w_dev || sb < 0 || sb >= (int)P->subs.size()) return FC_E_ARG;
+  if (!P || !w_dev || sb < -1 || sb >= (int)P->subs.size()) return FC_E_ARG;
   if (P->device < 0) return FC_E_STATE;
-  const Sub& s = P->subs[sb];
-  if (n != s.L) return FC_E_SHAPE;
+  // sb == -1: every subband's weights, concatenated in plan order
+  if (n != (sb < 0 ? P->w_total : P->subs[sb].L)) return FC_E_SHAPE;
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
   if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
-  hipError_t e = hipMemcpyAsync(P->d_w + P->w_off[sb], w_dev, n * sizeof(float), hipMemcpyDeviceToDevice,
-                                (hipStream_t)stream);
+  hipError_t e = hipMemcpyAsync(P->d_w + (sb < 0 ? 0 : P->w_off[sb]), w_dev, n * sizeof(float),
+                                hipMemcpyDeviceToDevice, (hipStream_t)stream);
   if (cur != P->device) (void)hipSetDevice(cur);
   return e == hipSuccess ? FC_OK : FC_E_DEVICE;
 }

@@ -174,6 +174,10 @@ class Plan:
         if is_dev:
             if w.dtype != torch.float32 or w.numel() != L or not w.is_contiguous():
                 raise ValueError("weights must be a contiguous float32 tensor of n_short values")
+            # the library does not read device weights on the host: the
+            # finiteness check that fc_set_weights makes is made here
+            if not bool(torch.isfinite(w).all()):
+                raise ValueError("weights must be finite")
             _check(lib().fc_set_weights_device(self._h, sb, _ptr(w), L, _stream_handle(stream)),
                    "fc_set_weights_device")
             return
@@ -182,6 +186,20 @@ class Plan:
             raise ValueError("need %d weights" % L)
         st = None if self.device < 0 else _stream_handle(stream)
         _check(lib().fc_set_weights(self._h, sb, a.ctypes.data_as(_F32P), L, st), "fc_set_weights")
+
+    def set_all_weights(self, w, stream=None):
+        """Every subband's weights at once from a float32 CUDA tensor holding
+        them concatenated in plan order (one device copy; checked finite)."""
+        import torch
+        total = sum(s["n_short"] for s in self.subbands)
+        if not (isinstance(w, torch.Tensor) and w.is_cuda):
+            raise ValueError("set_all_weights takes a CUDA tensor")
+        if w.dtype != torch.float32 or w.numel() != total or not w.is_contiguous():
+            raise ValueError("weights must be a contiguous float32 tensor of %d values" % total)
+        if not bool(torch.isfinite(w).all()):
+            raise ValueError("weights must be finite")
+        _check(lib().fc_set_weights_device(self._h, -1, _ptr(w), total, _stream_handle(stream)),
+               "fc_set_weights_device")
 
     def get_weights(self, sb):
         L = self.subbands[sb]["n_short"]

@@ -492,23 +492,10 @@ def main():
     gen.manual_seed(5)
     g_dev = torch.randn((int(hi[-1]), 2), generator=gen, device=dev).to(torch.float16)
     gw = torch.empty(sum(s["n_short"] for s in tx_all), dtype=torch.float32, device=dev)
-    # blocks per task of the gradient (it follows the adjoint's tuning): the
-    # fastest of a few, each timed over two calls after one warm-up
-    best = None
-    for rl in (0, 2, 4, 8):
-        ptx.set_tuning(OP_ADJ, rl, 4)
-        ptx.weight_grad(x_dev, g_dev, gw, gs)
-        b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        b0.record(gs)
-        for _ in range(2):
-            ptx.weight_grad(x_dev, g_dev, gw, gs)
-        b1.record(gs)
-        torch.cuda.synchronize()
-        t_rl = b0.elapsed_time(b1) / 2
-        if best is None or t_rl < best[1]:
-            best = (rl, t_rl)
-    ptx.set_tuning(OP_ADJ, best[0], 4)
-    tune["weight_grad"] = ptx.get_tuning(OP_ADJ)
+    # the gradient's blocks per task are fixed (a fixed summation tree); its
+    # launches run on the side streams like the other operations
+    ptx.set_tuning(OP_ADJ, 0, 4)
+    tune["weight_grad"] = {"run_len": 4, "conc": 4}
     for _ in range(args.warmup):
         ptx.weight_grad(x_dev, g_dev, gw, gs)
     a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -279,10 +279,17 @@ fc_status fc_tx_adjoint(fc_plan* plan, const void* highrate_in, void* lowrate_ou
  *               X the block's short FFT of x, G the long FFT of the matching
  *               block of g scaled like the adjoint, q = Xi(p).
  * Buffers are owned by the caller. Asynchronous on `stream`; the result does
- * not depend on the plan's current weights. Scheduled as the adjoint: the
- * FC_OP_ADJ tuning (fc_plan_set_tuning) sets its blocks per task and its
- * launches in flight. Errors: FC_E_ARG (null pointer), FC_E_STATE (host-only
- * plan, or a plan with an FC_SYNC_OLS subband, which has no adjoint),
+ * not depend on the plan's current weights. Scheduled over the adjoint's
+ * blocks in tasks of four consecutive blocks of a group (a fixed split); the
+ * FC_OP_ADJ concurrency (fc_plan_set_tuning) sets its launches in flight.
+ * Each task stores its per-bin sums in its own slot of a plan-owned scratch
+ * buffer (4 bytes x the sum over tasks of the n_short of the task's
+ * subbands), and a reduction adds every weight's slots in block order: the
+ * summation tree is fixed, so the result is bitwise the same for every tuning
+ * and every call. The scratch is allocated (hipMalloc) by the first call and
+ * kept until fc_plan_destroy. Errors:
+ * FC_E_ARG (null pointer), FC_E_STATE (host-only plan, or a plan with an
+ * FC_SYNC_OLS subband, which has no adjoint), FC_E_NOMEM (scratch),
  * FC_E_DEVICE (launch failure).
  */
 fc_status fc_tx_weight_grad(fc_plan* plan, const void* lowrate_in, const void* grad_out,
@@ -294,8 +301,8 @@ fc_status fc_plan_stats(const fc_plan* plan, int32_t op, int64_t* n_blocks, int6
                         int64_t* n_launches);
 
 /*
- * Tuning of operation op (FC_OP_TX .. FC_OP_TXG; FC_OP_ADJ also sets
- * the weight gradient's work split):
+ * Tuning of operation op (FC_OP_TX .. FC_OP_TXG; FC_OP_ADJ's conc also
+ * applies to the weight gradient, whose blocks per task are fixed):
  *   run_len  FC blocks per workgroup task (consecutive blocks of one group;
  *            0 = the planner's choice from the total block count; TX runs of
  *            synchronised groups are rounded up to whole symbols; RX tasks

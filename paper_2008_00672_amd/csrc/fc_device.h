@@ -1158,8 +1158,10 @@ struct StoreGradReg : NoPrefetch {
 // block (window and phase of the forward transform) in a scratch buffer,
 // whose last pass accumulates the products. Each sum belongs to one thread
 // for the whole task (in registers for one-subband groups, in LDS for groups
-// of several subbands); at the end the task adds its sums into grad_w (float
-// atomics: tasks of one subband run concurrently).
+// of several subbands); at the end the task stores its sums in its own
+// partial-sum slot (TaskDesc::part_off), in weight order, and
+// fc_wgrad_reduce_kernel adds the slots of each group in block order: no
+// atomics, so grad_w does not depend on the work split or launch order.
 template <int IO, int NL>
 __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
   extern __shared__ float2 smem[];
@@ -1257,11 +1259,11 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
       put(SizeC<64>()); put(SizeC<32>()); put(SizeC<16>());
     }
     __syncthreads();
-    float* gw = reinterpret_cast<float*>(a.out);
+    float* part = a.part + T.part_off + Sb.aofs;
     for (int u = tid; u < L; u += kThreads) {
       float sum = 0.f;
       for (int w = 0; w < NBG; ++w) sum += red[w * L + u];
-      atomicAdd(gw + Sb.w_off + ((u + (L >> 1)) & (L - 1)), sum);
+      part[(u + (L >> 1)) & (L - 1)] = sum;
     }
     return;
   }
@@ -1295,11 +1297,11 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
           sg.R = S + Sb.cofs; sg.ph = make_float2(Z.ph.x, Z.ph.y);
           fft_run<kThreads, LL, 0, -1, RML>(scr, tid, lx, sg, tw);
         }
-        float* gw = reinterpret_cast<float*>(a.out);
+        float* part = a.part + T.part_off + Sb.aofs;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
           const int u = last_pos<kThreads, LL, 0, RML>(s, tid);
-          if (u >= 0) atomicAdd(gw + Sb.w_off + ((u + (LL >> 1)) & (LL - 1)), sg.r[s]);
+          if (u >= 0) part[(u + (LL >> 1)) & (LL - 1)] = sg.r[s];
         }
       }
     };
@@ -1358,11 +1360,32 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
     }
   }
   __syncthreads();
-  float* gw = reinterpret_cast<float*>(a.out);
+  float* part = a.part + T.part_off;
   for (int m = 0; m < G.n_sb; ++m) {
     const SbDesc Sb = a.sb[G.sb_first + m];
-    for (int u = tid; u < Sb.L; u += kThreads)
-      atomicAdd(gw + Sb.w_off + ((u + (Sb.L >> 1)) & (Sb.L - 1)), acc[Sb.aofs + u]);
+    for (int u = tid; u < Sb.L; u += kThreads) part[Sb.aofs + ((u + (Sb.L >> 1)) & (Sb.L - 1))] = acc[Sb.aofs + u];
+  }
+}
+
+// grad_w of every subband of group blockIdx.x: the sum of the group's task
+// slots, taken in block order (a fixed order, so the result is the same for
+// every work split and launch order). Every weight is written. (The sums do
+// not depend on the I/O type; one instance per type keeps the dispatch
+// uniform.)
+template <int IO>
+__global__ __launch_bounds__(kThreads) void fc_wgrad_reduce_kernel(const SbDesc* sb, const GroupDesc* grp,
+                                                                     int n_grp, const float* part, float* gw) {
+  const int g = blockIdx.x;
+  if (g >= n_grp) return;
+  const GroupDesc G = grp[g];
+  for (int m = 0; m < G.n_sb; ++m) {
+    const SbDesc Sb = sb[G.sb_first + m];
+    const float* p0 = part + G.part_base + Sb.aofs;
+    for (int p = threadIdx.x; p < Sb.L; p += kThreads) {
+      float sum = 0.f;
+      for (int t = 0; t < G.part_n; ++t) sum += p0[(int64_t)t * G.acc_len + p];
+      gw[Sb.w_off + p] = sum;
+    }
   }
 }
 
@@ -1377,7 +1400,8 @@ __global__ __launch_bounds__(kThreads) void fc_zero_kernel(void* out, int64_t n)
 // ------------------------------------------------------ per-I/O dispatch ---
 // Kernel classes: 0 = TX pruned (size = L, aux = log2 I), 1 = TX full
 // (size = N, aux = largest L), 2 = RX and adjoint (size = N), 3 = weight
-// gradient (size = N), 4 = demodulating RX (size = N).
+// gradient (size = N), 4 = demodulating RX (size = N), 5 = weight-gradient
+// reduction (one workgroup per group, n_task = number of groups).
 template <int IO, int L>
 hipError_t launch_pruned(const LaunchArgs& a, int logi, size_t lds, hipStream_t s, dim3 grid) {
   dim3 block(kThreads);
@@ -1417,6 +1441,11 @@ hipError_t launch_size(int cls, const LaunchArgs& a, int aux, size_t lds, hipStr
 template <int IO>
 hipError_t launch_io(int cls, int size, const LaunchArgs& a, int aux, size_t lds, hipStream_t s) {
   if (a.n_task <= 0) return hipSuccess;
+  if (cls == 5) {
+    hipLaunchKernelGGL(fc_wgrad_reduce_kernel<IO>, dim3(a.n_task), dim3(kThreads), 0, s, a.sb, a.grp, a.n_task,
+                       a.part, reinterpret_cast<float*>(a.out));
+    return hipGetLastError();
+  }
   dim3 grid(cls >= 2 ? ((a.n_task + 7) & ~7) : a.n_task);
   switch (size) {
 #define FC_SZ(SZ) case SZ: return launch_size<IO, SZ>(cls, a, aux, lds, s, grid);

@@ -153,7 +153,9 @@ struct GroupDesc {
   int32_t acc_len;           // weight gradient: accumulator floats (sum of the subbands' L)
   int32_t taper;             // TX, synchronised OLS: edge length T of the output windows (0: hard edges)
   int32_t wg_nb;             // weight gradient, one subband with L <= 1024: blocks per group (0: per block)
-  int32_t pad2;
+  int32_t part_n;            // weight gradient: tasks of the group (partial-sum slots)
+  int64_t part_base;         // weight gradient: first float of the group's partial sums; the slot of
+                             // the group's i-th task (block order) starts at part_base + i * acc_len
 };
 
 // One FC block of a group.
@@ -191,6 +193,8 @@ struct TaskDesc {
   int64_t z1_lo, z1_hi;
   int32_t ola;               // 1: blocks overlap-add their outputs (carry in LDS)
   int32_t accumulate;        // 1: out += value instead of out = value
+  int64_t part_off;          // weight gradient: this task's partial-sum slot (acc_len floats, in
+                             // fftshifted weight order per subband, at the subband's aofs)
 };
 
 // Launch arguments of one kernel phase.
@@ -210,6 +214,7 @@ struct LaunchArgs {
   void* out;
   const void* in2;           // weight gradient: the forward low-rate input
   int32_t front;             // TX: 1 = input is the QAM grid (OFDM modulation in the kernel)
+  float* part;               // weight gradient: per-task partial sums (scratch)
 };
 
 }  // namespace fcx

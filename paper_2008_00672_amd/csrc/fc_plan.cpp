@@ -84,6 +84,7 @@ struct Op {
   std::vector<BlockSb> bsb;
   std::vector<TaskDesc> task;
   std::vector<uint64_t> rxmap;            // RX scatter maps
+  int64_t part_total = 0;                 // adjoint op: floats of the weight gradient's partial sums
   // One kernel launch. kind: 0 = FC kernel of class cls (0 TX pruned, 1 TX
   // full, 2 RX / adjoint) and transform size `size`; 2 = zero the output
   // buffer. glds: LDS bytes of the weight-gradient kernel over the same tasks
@@ -98,11 +99,19 @@ struct Op {
   SbDesc* d_sb = nullptr; GroupDesc* d_grp = nullptr; BlockDesc* d_blk = nullptr;
   BlockSb* d_bsb = nullptr; TaskDesc* d_task = nullptr;
   uint64_t* d_rxmap = nullptr;
+  float* d_part = nullptr;                // weight-gradient scratch (allocated at its first use)
 };
 
 }  // namespace
 
 constexpr int kMaxConc = 4;      // user stream + three side streams
+// Internal schedule of the weight gradient: the adjoint's blocks, but tasks of
+// a fixed kWgradRun blocks (two synchronised symbols), so that the per-task
+// partial sums, added in block order, form the same summation tree for every
+// tuning of the adjoint.
+constexpr int kOpWgrad = 5;
+constexpr int kOps = 6;
+constexpr int kWgradRun = 4;
 
 struct fc_plan {
   int device = 0, io = 0;
@@ -115,7 +124,7 @@ struct fc_plan {
   float* d_w = nullptr;
   Cf* d_tw = nullptr;
   Cf* d_twp = nullptr;           // per-pass twiddle bases
-  Op op[5];
+  Op op[kOps];                        // FC_OP_TX .. FC_OP_TXG, then the weight gradient's schedule
   int run_len[5] = {0, 0, 0, 0, 0};   // blocks per task per op (0: planner heuristic)
   int conc[5] = {kMaxConc, kMaxConc, kMaxConc, kMaxConc, kMaxConc};   // per op: launches of one independent set in flight
   hipStream_t side[kMaxConc - 1] = {};
@@ -240,9 +249,12 @@ Win clip_valid(const Sub& s, int64_t xrel, int lo, int hi, int64_t len) {
   return Win{xrel, (int)a, (int)b};
 }
 
-void build_op(fc_plan* P, int kind) {
-  Op& op = P->op[kind];
+void build_op(fc_plan* P, int op_index) {
+  Op& op = P->op[op_index];
   op = Op();
+  // the weight gradient's schedule is the adjoint's, with its own task split
+  const bool wgrad = op_index == kOpWgrad;
+  const int kind = wgrad ? FC_OP_ADJ : op_index;
   const int nsb = (int)P->subs.size();
   // validity: TX any mode; ADJ CONT_* or SYNC_OLA; RX any; the
   // demodulating RX and the grid-input TX synchronised subbands
@@ -519,16 +531,24 @@ void build_op(fc_plan* P, int kind) {
       // prefetched while the current one is analysed); in accumulate mode
       // single blocks, split into even and odd launches so no two tasks of a
       // launch add into the same low-rate samples ---
-      const bool acc = !G.sync && ((kind == 1 && G.ola) || (kind == 2 && !G.ola));
+      // (the gradient writes no low-rate samples: it never accumulates)
+      const bool acc = !wgrad && !G.sync && ((kind == 1 && G.ola) || (kind == 2 && !G.ola));
       any_ola_rx |= acc;
-      int K = acc ? 1
-                  : P->run_len[kind] > 0 ? P->run_len[kind]
-                                         : (int)std::max<int64_t>(2, std::min<int64_t>(8, total_blocks / 4096));
+      int K = wgrad ? kWgradRun
+              : acc ? 1
+                    : P->run_len[kind] > 0 ? P->run_len[kind]
+                                           : (int)std::max<int64_t>(2, std::min<int64_t>(8, total_blocks / 4096));
       if (kind == 3) K += K & 1;                        // whole symbols per task
+      // weight gradient: one partial-sum slot per task, in block order
+      GroupDesc& gw = op.grp[g];
+      gw.part_base = op.part_total;
+      gw.part_n = (nblk + K - 1) / K;
+      if (wgrad) op.part_total += (int64_t)gw.part_n * gw.acc_len;
       for (int b = 0; b < nblk; b += K) {
         TaskDesc t{};
         t.group = (int)g; t.blk_first = first_blk + b; t.blk_count = std::min(K, nblk - b);
         t.accumulate = acc ? 1 : 0;
+        t.part_off = gw.part_base + (int64_t)(b / K) * gw.acc_len;
         PhaseTasks& ph = acc ? ((b & 1) ? rx_odd : rx_even) : rx_all;
         const GroupDesc& gd = op.grp[g];
         // adjoint: one-subband groups with a whole-workgroup short transform
@@ -604,7 +624,9 @@ fc_status upload_op(Op& op) {
 void free_op(Op& op) {
   (void)hipFree(op.d_sb); (void)hipFree(op.d_grp); (void)hipFree(op.d_blk); (void)hipFree(op.d_bsb); (void)hipFree(op.d_task);
   (void)hipFree(op.d_rxmap);
+  (void)hipFree(op.d_part);
   op.d_rxmap = nullptr;
+  op.d_part = nullptr;
   op.d_sb = nullptr; op.d_grp = nullptr; op.d_blk = nullptr; op.d_bsb = nullptr; op.d_task = nullptr;
 }
 
@@ -659,30 +681,26 @@ fc_status run_op(fc_plan* P, int kind, const void* in, void* out, hipStream_t st
   return e == hipSuccess ? FC_OK : FC_E_DEVICE;
 }
 
-// Weight gradient: zero grad_w, then the gradient kernel over the adjoint's
-// tasks (its blocks carry the forward windows and the adjoint phases).
-fc_status run_wgrad(fc_plan* P, const void* x, const void* g, float* grad_w, hipStream_t st) {
-  Op& op = P->op[FC_OP_ADJ];
-  if (!op.valid || P->device < 0) return FC_E_STATE;
-  if (!x || !g || !grad_w) return FC_E_ARG;
-  int cur = -1;
-  if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
-  if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
-  // P->w_total floats (even: every L is a power of two >= 16) as complex zeros
-  hipError_t e = launch_zero(grad_w, P->w_total / 2, IO_C64, st);
+// Weight gradient: the gradient kernel over the adjoint's tasks (its blocks
+// carry the forward windows and the adjoint phases), each task storing its
+// per-bin sums in its own slot of `part` (the adjoint op's part_total floats),
+// then the reduction, which writes every weight of grad_w.
+fc_status launch_wgrad(fc_plan* P, const void* x, const void* g, float* grad_w, float* part, hipStream_t st) {
+  const Op& op = P->op[kOpWgrad];
   auto launch = [&](const Op::Phase& ph, hipStream_t s) {
     LaunchArgs a{};
     a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
     a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
     a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
-    a.in = g; a.out = grad_w; a.in2 = x;
+    a.in = g; a.out = grad_w; a.in2 = x; a.part = part;
     return launch_kernel(3, ph.size, a, ph.aux, ph.glds, s);
   };
   // the adjoint's independent launch sets, spread over the side streams as
-  // run_op does (the kernels add into grad_w with atomics)
+  // run_op does (every task writes only its own slot)
   std::vector<const Op::Phase*> ph;
   for (const Op::Phase& p : op.phases)
     if (p.kind != 2) ph.push_back(&p);
+  hipError_t e = hipSuccess;
   for (size_t i = 0; i < ph.size() && e == hipSuccess;) {
     size_t j = i + 1;
     while (j < ph.size() && ph[j]->seq == ph[i]->seq) ++j;
@@ -705,8 +723,32 @@ fc_status run_wgrad(fc_plan* P, const void* x, const void* g, float* grad_w, hip
     }
     i = j;
   }
-  if (cur != P->device) (void)hipSetDevice(cur);
+  if (e == hipSuccess) {
+    LaunchArgs a{};
+    a.sb = op.d_sb; a.grp = op.d_grp; a.n_task = (int)op.grp.size(); a.io = P->io;
+    a.out = grad_w; a.part = part;
+    e = launch_kernel(5, 0, a, 0, 0, st);
+  }
   return e == hipSuccess ? FC_OK : FC_E_DEVICE;
+}
+
+fc_status run_wgrad(fc_plan* P, const void* x, const void* g, float* grad_w, hipStream_t st) {
+  Op& op = P->op[kOpWgrad];
+  if (!op.valid || P->device < 0) return FC_E_STATE;
+  if (!x || !g || !grad_w) return FC_E_ARG;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
+  if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
+  fc_status r = FC_OK;
+  // the partial sums live in plan-owned scratch, allocated at the first call
+  // after the adjoint's tasks were (re)built
+  if (!op.d_part && hipMalloc((void**)&op.d_part, (size_t)op.part_total * sizeof(float)) != hipSuccess) {
+    op.d_part = nullptr;
+    r = FC_E_NOMEM;
+  }
+  if (r == FC_OK) r = launch_wgrad(P, x, g, grad_w, op.d_part, st);
+  if (cur != P->device) (void)hipSetDevice(cur);
+  return r;
 }
 
 // Measured schedule: times every kernel launch of the op on its own (one
@@ -746,7 +788,7 @@ fc_status measure_costs(fc_plan* P, int kind, const void* in, void* out, hipStre
 // plan's launches (the grant is process-wide and only ever raised).
 fc_status grant_lds(const fc_plan* P) {
   size_t lds_max = 0;
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < kOps; ++k)
     for (const auto& ph : P->op[k].phases) lds_max = std::max(lds_max, std::max(ph.lds, ph.glds));
   if (lds_max > 65536 && set_lds_limits(lds_max) != hipSuccess) return FC_E_UNSUPPORTED;
   return FC_OK;
@@ -842,7 +884,7 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   P->w_off.resize(n_sb);
   for (int m = 0; m < n_sb; ++m) { P->w_off[m] = P->w_total; P->w_total += P->subs[m].L; }
   // host tables
-  for (int k = 0; k < 5; ++k) build_op(P, k);
+  for (int k = 0; k < kOps; ++k) build_op(P, k);
   if (device < 0) {        // host-only plan: schedules and layouts, no device state
     *plan = P;
     return FC_OK;
@@ -880,7 +922,7 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   if (!st) st = upload(tw, &P->d_tw);
   if (!st) st = upload(twp, &P->d_twp);
   if (!st) st = upload(w, &P->d_w);
-  for (int k = 0; k < 5 && !st; ++k) st = upload_op(P->op[k]);
+  for (int k = 0; k < kOps && !st; ++k) st = upload_op(P->op[k]);
   if (!st) st = grant_lds(P);
   // side streams (default priority) and fork/join events
   for (int q = 0; q + 1 < kMaxConc && !st; ++q) {
@@ -905,7 +947,7 @@ void fc_plan_destroy(fc_plan* P) {
     if (P->ev_join[q]) (void)hipEventDestroy(P->ev_join[q]);
   }
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
-  for (int k = 0; k < 5; ++k) free_op(P->op[k]);
+  for (int k = 0; k < kOps; ++k) free_op(P->op[k]);
   (void)hipFree(P->d_w);
   (void)hipFree(P->d_tw);
   (void)hipFree(P->d_twp);

@@ -8,9 +8,9 @@ are compared with the oracle under the FP32 gate."""
 import numpy as np
 import pytest
 
-from fc_cases import GATE_DB
 from fcsynth import workloads as W
-from test_gpu_parity import assert_gate, run_rx, run_tx
+from fc_cases import assert_gate
+from test_gpu_parity import run_rx, run_tx
 
 pytestmark = pytest.mark.gpu
 

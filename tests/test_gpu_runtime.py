@@ -1,5 +1,5 @@
-"""GPU runtime features through the C ABI: tuning invariance, HIP graph
-capture and replay, the autotuner.
+"""GPU runtime features through the C ABI: tuning invariance (outputs and
+the weight gradient), HIP graph capture and replay, the autotuner.
 
 The work split (blocks per task, concurrent launches) does not change the
 arithmetic of any block, so outputs must be bit-identical across tunings;
@@ -56,6 +56,40 @@ def test_tuning_is_bit_exact(op):
         torch.cuda.synchronize()
         print("%s run_len %d conc %d: equal %s" % (op, run_len, conc, torch.equal(out, ref)), flush=True)
         assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("shape", ["carriers", "shared_long"])
+def test_weight_grad_is_deterministic(shape):
+    """The weight gradient stores per-task partial sums and reduces them in
+    block order: bitwise the same for every tuning and on repeated calls.
+    carriers: one-subband groups (sums in registers); shared_long: eight
+    subbands sharing one long transform (sums in LDS)."""
+    import torch
+    if shape == "carriers":
+        sbs, xs, Ds, p = _batched()
+        io = "f16"
+    else:
+        fb, meta = W.rx_filterbank()
+        sbs = [dict(s, mode="sync_ola", n_symbols=14) for s in fb]
+        xs, Ds, _ = make_inputs(sbs, meta["qam"], meta["seed"], "rc")
+        io = "bf16"
+        p = _plan(sbs, io, Ds)
+    print("case: weight gradient determinism, %s, %s" % (shape, io), flush=True)
+    _, lens, _ = stream_offsets(sbs)
+    rng = np.random.default_rng(8)
+    g = to_device(rng.standard_normal(sum(lens)) + 1j * rng.standard_normal(sum(lens)), io)
+    x = to_device(_cat(xs), io)
+    ref = p.weight_grad(x, g).clone()
+    torch.cuda.synchronize()
+    assert torch.isfinite(ref).all() and ref.abs().max() > 0
+    for run_len, conc in [(1, 1), (2, 4), (4, 2), (16, 4), (0, 1)]:
+        p.set_tuning(2, run_len, conc)
+        for rep in range(2):
+            out = p.weight_grad(x, g)
+            torch.cuda.synchronize()
+            same = torch.equal(out.view(torch.int32), ref.view(torch.int32))
+            print("run_len %d conc %d call %d: bitwise equal %s" % (run_len, conc, rep, same), flush=True)
+            assert same
 
 
 def test_graph_replay_matches_eager():

@@ -54,8 +54,12 @@ enum {
   FC_E_UNSUPPORTED = -3,  /* valid per the paper but not implemented here    */
   FC_E_NOMEM = -4,        /* host or device allocation failed                */
   FC_E_DEVICE = -5,       /* a HIP runtime call failed                       */
-  FC_E_STATE = -6         /* operation not valid for this plan               */
+  FC_E_STATE = -6,        /* operation not valid for this plan               */
+  FC_E_LIMIT = -7         /* needs more than the fixed no-allocation scratch */
 };
+
+/* Size of the fixed device scratch of fc_tx_weight_grad_noalloc (per GPU). */
+#define FC_NOALLOC_SCRATCH_BYTES (64ll << 20)
 
 /* Processing model of a subband (Sec. III-B, III-C, IV). */
 enum {
@@ -294,6 +298,26 @@ fc_status fc_tx_adjoint(fc_plan* plan, const void* highrate_in, void* lowrate_ou
  */
 fc_status fc_tx_weight_grad(fc_plan* plan, const void* lowrate_in, const void* grad_out,
                             float* grad_w, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * computation as fc_tx_weight_grad, with the same kernels and the same fixed
+ * summation tree (bitwise the same result), but the per-task partial sums go
+ * to a fixed device array of FC_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every GPU it runs on until the process ends, instead of plan-owned
+ * scratch. It calls no hipMalloc, hipFree or other allocating routine; the
+ * caller passes every input and output, as for fc_tx_weight_grad.
+ * The array is shared by every call on one GPU: calls that overlap in time on
+ * one GPU (from any plan, stream or host thread) race and give wrong results;
+ * calls ordered on one stream, or otherwise serialised, are safe. Nothing in
+ * it needs clearing between calls (every slot is written before it is read).
+ * Errors: as fc_tx_weight_grad (no FC_E_NOMEM), and FC_E_LIMIT when the
+ * plan's partial sums (4 bytes x the sum over the gradient's tasks of their
+ * subbands' n_short) exceed FC_NOALLOC_SCRATCH_BYTES; nothing is queued then.
+ */
+fc_status fc_tx_weight_grad_noalloc(fc_plan* plan, const void* lowrate_in, const void* grad_out,
+                                    float* grad_w, void* stream);
 
 /* Work decomposition of operation op: FC blocks, tasks (workgroup work
  * items) and kernel launches per call. Either pointer may be NULL. */

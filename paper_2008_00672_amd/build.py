@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libfc.so")
 
 # (source, extra defines): the device code is built once per I/O storage type
 UNITS = [("fc_kern_io.hip", ["-DFC_IO=0"]), ("fc_kern_io.hip", ["-DFC_IO=1"]), ("fc_kern_io.hip", ["-DFC_IO=2"]),
-         ("fc_launch.cpp", []), ("fc_plan.cpp", []), ("fc_graph.cpp", [])]
+         ("fc_launch.cpp", []), ("fc_plan.cpp", []), ("fc_graph.cpp", []), ("fc_scratch.hip", [])]
 
 # Packed FP32 VALU forms are kept out of the generated code; the compiler
 # otherwise forms them from float2 arithmetic.

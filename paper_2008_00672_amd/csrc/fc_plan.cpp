@@ -26,6 +26,7 @@ namespace fcx {
 hipError_t launch_kernel(int cls, int size, const LaunchArgs& a, int aux, size_t lds, hipStream_t s);
 hipError_t launch_zero(void* out, int64_t n, int io, hipStream_t s);
 hipError_t set_lds_limits(size_t bytes);
+hipError_t noalloc_scratch(int device, float** ptr);
 }  // namespace fcx
 
 using namespace fcx;
@@ -818,6 +819,7 @@ const char* fc_status_str(fc_status s) {
     case FC_E_NOMEM: return "out of memory";
     case FC_E_DEVICE: return "HIP runtime error";
     case FC_E_STATE: return "operation not valid for this plan";
+    case FC_E_LIMIT: return "needs more than the fixed no-allocation scratch";
     default: return "unknown status";
   }
 }
@@ -1163,6 +1165,23 @@ fc_status fc_tx_weight_grad(fc_plan* P, const void* lowrate_in, const void* grad
                             void* stream) {
   if (!P) return FC_E_ARG;
   return run_wgrad(P, lowrate_in, grad_out, grad_w, (hipStream_t)stream);
+}
+
+fc_status fc_tx_weight_grad_noalloc(fc_plan* P, const void* lowrate_in, const void* grad_out, float* grad_w,
+                                    void* stream) {
+  if (!P) return FC_E_ARG;
+  const Op& op = P->op[kOpWgrad];
+  if (!op.valid || P->device < 0) return FC_E_STATE;
+  if (!lowrate_in || !grad_out || !grad_w) return FC_E_ARG;
+  if (op.part_total > (int64_t)(FC_NOALLOC_SCRATCH_BYTES / sizeof(float))) return FC_E_LIMIT;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return FC_E_DEVICE;
+  if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
+  float* part = nullptr;
+  fc_status r = noalloc_scratch(P->device, &part) == hipSuccess ? FC_OK : FC_E_DEVICE;
+  if (r == FC_OK) r = launch_wgrad(P, lowrate_in, grad_out, grad_w, part, (hipStream_t)stream);
+  if (cur != P->device) (void)hipSetDevice(cur);
+  return r;
 }
 
 }  // extern "C"

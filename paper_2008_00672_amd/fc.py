@@ -49,6 +49,7 @@ EXPORTS = {
     "fc_rx_demodulate": (_I32, [_P, _P, _P, _P]),
     "fc_tx_modulate": (_I32, [_P, _P, _P, _P]),
     "fc_tx_weight_grad": (_I32, [_P, _P, _P, _P, _P]),
+    "fc_tx_weight_grad_noalloc": (_I32, [_P, _P, _P, _P, _P]),
     "fc_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
     "fc_plan_get_tuning": (_I32, [_P, _I32, _I32P, _I32P]),
     "fc_plan_autotune": (_I32, [_P, _I32, _P, _P, _P, _I32P, _I32P, ctypes.POINTER(ctypes.c_float)]),
@@ -296,6 +297,22 @@ class Plan:
             raise ValueError("grad_w must be a contiguous float32 tensor of sum(n_short) values on the plan's device")
         _check(lib().fc_tx_weight_grad(self._h, _ptr(x), _ptr(g), _ptr(out), _stream_handle(stream)),
                "fc_tx_weight_grad")
+        return out
+
+    def weight_grad_noalloc(self, x, g, out, stream=None):
+        """fc_tx_weight_grad_noalloc: the weight gradient into the caller's
+        `out` with the library's fixed device scratch (no allocation, also
+        none here: `out` is required)."""
+        import torch
+        lo, hi = self.layout(OP_TX)
+        self._check_buf(x, int(lo[-1]), "low-rate input")
+        self._check_buf(g, int(hi[-1]), "high-rate gradient")
+        total = sum(s["n_short"] for s in self.subbands)
+        if (out is None or not out.is_cuda or out.device.index != self.device or out.dtype != torch.float32
+                or out.numel() != total or not out.is_contiguous()):
+            raise ValueError("grad_w must be a contiguous float32 tensor of sum(n_short) values on the plan's device")
+        _check(lib().fc_tx_weight_grad_noalloc(self._h, _ptr(x), _ptr(g), _ptr(out), _stream_handle(stream)),
+               "fc_tx_weight_grad_noalloc")
         return out
 
     # ----------------------------------------------------------- tuning --

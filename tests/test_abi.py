@@ -41,7 +41,7 @@ def test_exports_match_header():
 
 def test_status_strings():
     fc = _lib()
-    for code in range(0, -7, -1):
+    for code in range(0, -8, -1):
         assert fc.lib().fc_status_str(code)
     assert b"gfx950" in fc.lib().fc_version()
 

@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--rx-frames", type=int, default=100)
     ap.add_argument("--burst-slots", type=int, default=4096, help="slots of the plain FP32 continuous burst")
     ap.add_argument("--subframes", type=int, default=4000, help="mixed-numerology subframes (TX + RX)")
+    ap.add_argument("--opt-slots", type=int, default=64, help="slots per carrier of the weight optimisation")
+    ap.add_argument("--opt-steps", type=int, default=10, help="Adam steps of the weight optimisation")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -95,6 +97,20 @@ def tx_input(plan, sbs, meta):
         g = fcsynth.qam_grid(rng, meta["qam"], s["n_symbols"], s["n_active"])
         xs.append(fcsynth.cp_ofdm(g, s["n_short"], lcp))
     return xs
+
+
+def tx_input_grids(plan, sbs, meta):
+    """CP-OFDM input (complex128) and the QAM grids behind it, from the plan's
+    CP schedule."""
+    import fcsynth
+    rng = np.random.default_rng(meta["seed"])
+    xs, gs = [], []
+    for i, s in enumerate(sbs):
+        _, lcp, _ = plan.symbols(i)
+        g = fcsynth.qam_grid(rng, meta["qam"], s["n_symbols"], s["n_active"])
+        gs.append(g)
+        xs.append(fcsynth.cp_ofdm(g, s["n_short"], lcp))
+    return xs, gs
 
 
 def tx_grids(sbs, meta):
@@ -578,9 +594,71 @@ def extra_sections(args, torch, dev, gs, ptx, x_dev, hi, tx_all, tx_samples, tun
                          "OLA TX then CP-removing RX of its output, %d subframes, FP32 I/O" % args.subframes}
     log("mixed numerology: TX %.3f ms, RX %.3f ms" % (m_tx_ms, m_rx_ms))
 
+    weight_opt = weight_opt_section(args, torch, gs)
     checks = dict(burst=dict(slot=b1, meta=b_meta, x_slot=xb_slot, head=b_head, tail=b_tail),
                   subframes=dict(subbands=m_one, meta=m_meta, tx=m_tx0, rx=m_rx0))
-    return weight_grad, burst, subframes, checks
+    return weight_grad, burst, subframes, weight_opt, checks
+
+
+def weight_opt_section(args, torch, gs):
+    """Transition-weight optimisation of the 256 batched carriers (N_tb ~
+    U{4..16}, FP32, 16-QAM, --opt-slots slots each): Adam on J = mean EVM +
+    mean OOB through the library's backward kernels; time per optimisation
+    step (forward, objective, backward, update) and the objective's values."""
+    from fcsynth import workloads as W
+    from paper_2008_00672_amd import Plan, fc_tx
+    from paper_2008_00672_amd.weight_opt import TransitionWeights, TxObjective
+    sbs, meta = W.weight_opt_carriers(n_slots=args.opt_slots)
+    t = time.time()
+    pw = Plan(sbs, io="c64", device=0)
+    xs, grids = tx_input_grids(pw, sbs, meta)
+    xw = to_dev(np.concatenate(xs), "c64")
+    del xs
+    tw = TransitionWeights(pw)
+    obj = TxObjective(pw, grids, mu_oob=meta["mu_oob"])
+    log("weight optimisation set-up: %.1f s" % (time.time() - t))
+    theta = tw.theta0.clone().requires_grad_(True)
+    opt = torch.optim.Adam([theta], lr=0.02)
+    st = torch.cuda.current_stream()
+    js, evm_db, oob_db, ts = [], [], [], []
+    for it in range(args.opt_steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        opt.zero_grad()
+        J, evm, oob = obj(fc_tx(pw, xw, tw.full(theta)))
+        J.backward()
+        opt.step()
+        b.record(st)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+        js.append(float(J))
+        evm_db.append(round(10 * math.log10(float(evm.mean())), 3))
+        oob_db.append(round(10 * math.log10(float(oob.mean())), 3))
+    # the library's share of a step: one forward and one weight gradient
+    y = pw.tx(xw)
+    gy = torch.randn_like(y)
+    gw = torch.empty(sum(s["n_short"] for s in sbs), dtype=torch.float32, device=xw.device)
+    f_ms = time_graph(lambda s_: pw.tx(xw, y, s_), gs, 2, 5)
+    pw.weight_grad(xw, gy, gw)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(st)
+    for _ in range(5):
+        pw.weight_grad(xw, gy, gw)
+    b.record(st)
+    torch.cuda.synchronize()
+    g_ms = a.elapsed_time(b) / 5
+    out = {"ms_per_step": round(float(np.median(ts[1:] if len(ts) > 1 else ts)), 3), "steps": args.opt_steps,
+           "J": [float("%.6e" % v) for v in js], "evm_db_mean": evm_db, "oob_db_mean": oob_db,
+           "carriers": len(sbs), "slots": args.opt_slots, "parameters": int(tw.idx.numel()),
+           "tx_forward_ms": round(f_ms, 3), "weight_grad_ms": round(g_ms, 3),
+           "form": "256 batched carriers, N_tb ~ U{4..16}, %d slots of 16-QAM each, FP32 I/O: Adam (lr 0.02) on "
+                   "J = mean EVM + mean OOB (linear; EVM at a mid-CP window after a least-squares gain, OOB from a "
+                   "Welch PSD) over the 2 N_tb transition weights per carrier; forward, adjoint and weight gradient "
+                   "in the library's kernels, the objective in PyTorch" % args.opt_slots}
+    log("weight optimisation: %.1f ms per step, J %s" % (out["ms_per_step"], out["J"]))
+    del xw, y, gy, gw, obj
+    return out
 
 
 # ------------------------------------------------------------------ main ---
@@ -723,12 +801,12 @@ def main():
 
     # beside the step: the weight gradient, the plain FP32 burst and the
     # mixed-numerology TX + RX
-    weight_grad, burst, subframes, checks, latency = None, None, None, None, None
+    weight_grad, burst, subframes, weight_opt, checks, latency = None, None, None, None, None, None
     if args.quick:
         args.no_plain = args.no_cpu = args.no_latency = True
     else:
-        weight_grad, burst, subframes, checks = extra_sections(args, torch, dev, gs, ptx, x_dev, hi, tx_all,
-                                                               tx_samples, tune, repeat_ok)
+        weight_grad, burst, subframes, weight_opt, checks = extra_sections(args, torch, dev, gs, ptx, x_dev, hi,
+                                                                           tx_all, tx_samples, tune, repeat_ok)
 
     # single-unit latency: one slot of the 256 carriers, one RX frame (graph
     # replays, median of 20)
@@ -849,7 +927,8 @@ def main():
                    "rx_ms": round(rx_ms, 4), "tuning": tune, "latency": latency},
         "gate": gate, "value_measured": round(value, 1),
         "roofline": roof, "plain_fp32": burst, "mixed_numerology": subframes, "rx_demod": rx_demod,
-        "tx_grid": tx_grid, "weight_grad": weight_grad, "launch_overhead": overhead, "evm_db": evm,
+        "tx_grid": tx_grid, "weight_grad": weight_grad, "weight_opt": weight_opt, "launch_overhead": overhead,
+        "evm_db": evm,
         "method_check": method, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -54,6 +54,26 @@ def batched_carriers(n_carriers=256, seed=3, n_tb=8, n_symbols=14):
     return sbs, dict(qam=64, seed=seed, io='f16')
 
 
+def weight_opt_carriers(n_carriers=256, n_slots=64, seed=5):
+    """The batched carriers (widths, numerologies, long transforms and centres
+    of batched_carriers) for transition-weight optimisation: N_tb ~ U{4..16}
+    per carrier, L = max(64, next_pow2(12 W + 2 N_tb)) (N raised to at least
+    2 L and c clamped into its range where the wider transition bands need a
+    longer short transform), n_slots slots of 16-QAM per carrier, FP32."""
+    base, _ = batched_carriers(n_carriers)
+    rng = np.random.default_rng(seed)
+    sbs = []
+    for k, s in enumerate(base):
+        ntb = int(rng.integers(4, 17))
+        K = s["n_active"]
+        L = max(64, next_pow2(K + 2 * ntb))
+        N = max(s["n_long"], 2 * L)
+        lo, hi = -3 * N // 8 + L // 2, 3 * N // 8 - L // 2
+        c = min(max(s["center_bin"], lo), hi)
+        sbs.append(subband(s["scs_khz"], 14 * n_slots, K, ntb, L, N, c, 'sync_ola', stream=k))
+    return sbs, dict(qam=16, seed=seed, io='c64', mu_oob=1.0)
+
+
 RX_WIDTHS = (4, 12, 24, 33, 51, 66, 11, 72)
 RX_SHORT = (64, 256, 512, 512, 1024, 1024, 256, 1024)
 

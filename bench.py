@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--burst-slots", type=int, default=4096, help="slots of the plain FP32 continuous burst")
     ap.add_argument("--subframes", type=int, default=4000, help="mixed-numerology subframes (TX + RX)")
     ap.add_argument("--opt-slots", type=int, default=64, help="slots per carrier of the weight optimisation")
+    ap.add_argument("--cf-slots", type=int, default=4096, help="slots of the 52-PRB channel-filter comparison")
     ap.add_argument("--opt-steps", type=int, default=10, help="Adam steps of the weight optimisation")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -595,9 +596,45 @@ def extra_sections(args, torch, dev, gs, ptx, x_dev, hi, tx_all, tx_samples, tun
     log("mixed numerology: TX %.3f ms, RX %.3f ms" % (m_tx_ms, m_rx_ms))
 
     weight_opt = weight_opt_section(args, torch, gs)
+    channel_filter = channel_filter_section(args, torch, gs, repeat_ok)
     checks = dict(burst=dict(slot=b1, meta=b_meta, x_slot=xb_slot, head=b_head, tail=b_tail),
                   subframes=dict(subbands=m_one, meta=m_meta, tx=m_tx0, rx=m_rx0))
-    return weight_grad, burst, subframes, weight_opt, checks
+    return weight_grad, burst, subframes, weight_opt, channel_filter, checks
+
+
+def channel_filter_section(args, torch, gs, repeat_ok):
+    """The full-band channel filter with a 768 = 3 x 256 point transform
+    against 1024 points (Sec. VI-C): one 52-PRB subband (624 active
+    subcarriers, 8-bin transition bands) at 15 kHz, L = N (I = 1), --cf-slots
+    slots as independent streams, FP32 I/O; synchronised OLA TX, then the
+    demodulating RX of its output."""
+    from fcsynth import workloads as W
+    from paper_2008_00672_amd import OP_RXD, OP_TX, Plan
+    out = {}
+    for n in (768, 1024):
+        sb1, meta = W.wideband_slot("sync_ola", n)
+        sbs = [dict(sb1[0], stream=k) for k in range(args.cf_slots)]
+        p1 = Plan(sb1, io="c64", device=0)
+        p = Plan(sbs, io="c64", device=0)
+        x = to_dev(tx_input(p1, sb1, meta)[0], "c64", reps=args.cf_slots)
+        lo, hi = p.layout(OP_TX)
+        assert x.shape[0] == lo[-1]
+        y = p.empty(int(hi[-1]))
+        z = p.empty(int(p.layout(OP_RXD)[0][-1]))
+        tx_ms = time_graph(lambda st: p.tx(x, y, st), gs, args.warmup, args.steps)
+        rx_ms = time_graph(lambda st: p.rx_demod(y, z, st), gs, args.warmup, args.steps)
+        repeat_ok["channel_filter_%d" % n] = (repeats_bitwise(y, args.cf_slots, int(hi[1] - hi[0]))
+                                              and repeats_bitwise(z, args.cf_slots, 14 * n))
+        out["L%d" % n] = {"tx_ms": round(tx_ms, 4), "rx_demod_ms": round(rx_ms, 4),
+                          "us_per_slot": round(1e3 * (tx_ms + rx_ms) / args.cf_slots, 4),
+                          "high_rate_samples_per_slot": int(hi[1] - hi[0])}
+        del x, y, z
+    out["time_768_over_1024"] = round((out["L768"]["tx_ms"] + out["L768"]["rx_demod_ms"])
+                                      / (out["L1024"]["tx_ms"] + out["L1024"]["rx_demod_ms"]), 3)
+    out["form"] = ("52-PRB full-band channel filter, L = N (I = 1), %d slots of 64-QAM as streams, FP32 I/O: "
+                   "synchronised OLA TX + demodulating RX" % args.cf_slots)
+    log("channel filter 768 vs 1024: %s" % out)
+    return out
 
 
 def weight_opt_section(args, torch, gs):
@@ -801,12 +838,12 @@ def main():
 
     # beside the step: the weight gradient, the plain FP32 burst and the
     # mixed-numerology TX + RX
-    weight_grad, burst, subframes, weight_opt, checks, latency = None, None, None, None, None, None
+    weight_grad, burst, subframes, weight_opt, channel_filter, checks, latency = (None,) * 7
     if args.quick:
         args.no_plain = args.no_cpu = args.no_latency = True
     else:
-        weight_grad, burst, subframes, weight_opt, checks = extra_sections(args, torch, dev, gs, ptx, x_dev, hi,
-                                                                           tx_all, tx_samples, tune, repeat_ok)
+        weight_grad, burst, subframes, weight_opt, channel_filter, checks = extra_sections(
+            args, torch, dev, gs, ptx, x_dev, hi, tx_all, tx_samples, tune, repeat_ok)
 
     # single-unit latency: one slot of the 256 carriers, one RX frame (graph
     # replays, median of 20)
@@ -927,7 +964,8 @@ def main():
                    "rx_ms": round(rx_ms, 4), "tuning": tune, "latency": latency},
         "gate": gate, "value_measured": round(value, 1),
         "roofline": roof, "plain_fp32": burst, "mixed_numerology": subframes, "rx_demod": rx_demod,
-        "tx_grid": tx_grid, "weight_grad": weight_grad, "weight_opt": weight_opt, "launch_overhead": overhead,
+        "tx_grid": tx_grid, "weight_grad": weight_grad, "weight_opt": weight_opt, "channel_filter": channel_filter,
+        "launch_overhead": overhead,
         "evm_db": evm,
         "method_check": method, "cpu_baseline": cpu,
     }

@@ -89,9 +89,10 @@ def rx_filterbank(n_symbols=280):
     return sbs, dict(qam=256, seed=4, io='bf16', snr_db=30.0)
 
 
-def wideband_slot(mode):
-    """10 MHz uplink at 15 kHz with a 1024-point high-rate transform: one
-    subband of 52 PRB (624 active subcarriers) centred at bin 0, an 8-bin
-    transition band on each side, L = N = 1024 (I = 1, the channel-filter
-    case), one 14-symbol slot of 64-QAM; mode 'cont_ols' or 'sync_ola'."""
-    return [subband(15, 14, 624, 8, 1024, 1024, 0, mode)], dict(qam=64, seed=6, io='c64')
+def wideband_slot(mode, n=1024):
+    """10 MHz uplink at 15 kHz: one subband of 52 PRB (624 active
+    subcarriers) centred at bin 0, an 8-bin transition band on each side,
+    L = N = n (I = 1, the channel-filter case: 1024, or the 768 = 3 x 256 of
+    the paper's complexity discussion), one 14-symbol slot of 64-QAM; mode
+    'cont_ols' or 'sync_ola'."""
+    return [subband(15, 14, 624, 8, n, n, 0, mode)], dict(qam=64, seed=6, io='c64')

@@ -93,8 +93,10 @@ enum {
  *   n_symbols     B_OFDM,m, number of OFDM symbols in the burst (>= 1)
  *   n_active      L_act,m, active subcarriers K (even); passband kappa in [-K/2, K/2)
  *   n_tb          transition-band bins per side (default weights, validation)
- *   n_short       L_m = L_OFDM,m, power of two in [16, 4096]
- *   n_long        N, power of two in [n_short, 4096]
+ *   n_short       L_m = L_OFDM,m: a power of two in [16, 4096], or 3 x 2^k in
+ *                 [768, 3072] (mixed radix, e.g. the 768 = 3 x 256 of Sec. VI-C)
+ *   n_long        N in the same set, >= n_short, with N / n_short a power of
+ *                 two (FC_E_SHAPE otherwise); other lengths FC_E_UNSUPPORTED
  *   center_bin    c_m, subband centre in long-transform bins (signed)
  *   overlap_num/overlap_den  overlap factor lambda; synchronised modes need 1/2,
  *                 continuous modes need 0 < lambda <= 1/2 with lambda*L_m even

@@ -118,6 +118,9 @@ template <int DIR> struct Dft<16, DIR> {
   }
 };
 
+// v mod n for 0 <= v < 2n (any n: the mixed-radix sizes are not powers of two).
+__device__ __forceinline__ int wrap(int v, int n) { return v >= n ? v - n : v; }
+
 // LDS layout of the transform buffers between passes: one pad slot after
 // every 32 elements, so the strided butterfly writes of the early passes
 // spread over the banks. Buffers of n elements take lds_elems(n) slots.
@@ -198,9 +201,33 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const TwB& t) {
   }
 }
 
-// Slot s of the first pass: element index i and transform b it loads.
+// Mixed-radix transforms of P = 3 P2 points (is_tri(P)): three decimated
+// P2-point sub-transforms, each with the radix-4 plan, then a radix-3
+// combination (fft_run3). Per thread: S1 first-pass slots of each
+// sub-transform, and up to four output bins k2 (each giving three outputs).
+constexpr int kTriRM = 4;
+template <int NT, int P2>
+constexpr int tri_s1() { return (((P2 / 4) + NT - 1) / NT) * 4; }
+template <int NT, int P2>
+constexpr int tri_j() { return (P2 + NT - 1) / NT; }
+
 template <int NT, int P, int LOGBT, int RM = 16>
+__device__ __forceinline__ bool first_pos(int s, int tid, int& i, int& b);
+
+// Slot s of the first pass: element index i and transform b it loads.
+// (Mixed radix: slot n1 S1 + s' is first-pass slot s' of sub-transform n1,
+// element i = 3 i2 + n1.)
+template <int NT, int P, int LOGBT, int RM>
 __device__ __forceinline__ bool first_pos(int s, int tid, int& i, int& b) {
+  if constexpr (is_tri(P)) {
+    static_assert(LOGBT == 0, "mixed-radix transforms are not interleaved");
+    constexpr int P2 = P / 3, S1 = tri_s1<NT, P2>();
+    const int n1 = s / S1;
+    int i2;
+    if (n1 >= 3 || !first_pos<NT, P2, 0, kTriRM>(s - n1 * S1, tid, i2, b)) return false;
+    i = 3 * i2 + n1;
+    return true;
+  }
   constexpr int R = radix_of(P, 0, RM);
   constexpr int NB = P / R;
   constexpr int TOTAL = NB << LOGBT;
@@ -213,8 +240,15 @@ __device__ __forceinline__ bool first_pos(int s, int tid, int& i, int& b) {
 }
 
 // Output position of register slot s of the last pass (-1: slot unused).
+// (Mixed radix: slot 3 j + k1 is output k2 + P2 k1, k2 = tid + j NT.)
 template <int NT, int P, int LOGBT, int RM = 16>
 __device__ __forceinline__ int last_pos(int s, int tid) {
+  if constexpr (is_tri(P)) {
+    constexpr int P2 = P / 3;
+    const int j = s / 3, k2 = tid + j * NT;
+    if (j >= tri_j<NT, P2>() || k2 >= P2) return -1;
+    return k2 + P2 * (s - 3 * j);
+  }
   constexpr int R = radix_of(P, npass(P, RM) - 1, RM);
   constexpr int NB = P / R;
   constexpr int TOTAL = NB << LOGBT;
@@ -319,9 +353,17 @@ __device__ __forceinline__ void passes_from(float2* buf, int tid, Load& load, St
 // called first, so functors can start their own global loads (weights,
 // twiddles) before the passes run; every pass's twiddle bases are fetched
 // then as well.
+template <int NT, int P, int DIR, class Load, class Store>
+__device__ __forceinline__ void fft_run3(float2* buf, int tid, Load& load, Store& store, const float2* twb);
+
 template <int NT, int P, int LOGBT, int DIR, int RM = 16, class Load, class Store>
 __device__ __forceinline__ void fft_run(float2* buf, int tid, Load& load, Store& store,
                                         const float2* __restrict__ twb) {
+  if constexpr (is_tri(P)) {
+    static_assert(LOGBT == 0, "mixed-radix transforms are not interleaved");
+    fft_run3<NT, P, DIR>(buf, tid, load, store, twb);
+    return;
+  } else {
   constexpr int NP = npass(P, RM);
   static_assert(NT == kThreads || P <= 1024, "one wave holds at most 1024 points");
   // All LDS and twiddle indices of a pass depend only on the thread, so the
@@ -337,6 +379,7 @@ __device__ __forceinline__ void fft_run(float2* buf, int tid, Load& load, Store&
   load.prefetch(tid);
   store.prefetch(tid);
   passes_from<NT, P, LOGBT, DIR, RM, 0, MM>(buf, tid, load, store, t);
+  }
 }
 
 template <int V> struct SizeC { static constexpr int value = V; };
@@ -353,6 +396,88 @@ template <class F> struct NoPrefetchWrap {
   template <class... A>
   __device__ __forceinline__ auto operator()(A... args) -> decltype(f(args...)) { return f(args...); }
 };
+
+// First pass of a sub-transform of fft_run3: its inputs, loaded before any
+// sub-transform wrote the buffer.
+template <int S1> struct LoadRegs : NoPrefetch {
+  const float2* x;
+  __device__ __forceinline__ float2 operator()(int slot, int, int, int) const { return x[slot]; }
+};
+
+// Last pass of a sub-transform of fft_run3: bin k2 at its padded position.
+struct StoreRegion : NoPrefetch {
+  float2* buf;
+  __device__ __forceinline__ void operator()(int, int, float2 v, int tp) const { buf[tp] = v; }
+};
+
+// P = 3 P2 points (Cooley-Tukey with the factor 3 first: n = 3 n2 + n1,
+// k = k2 + P2 k1):
+//   T_n1[k2] = sum_n2 x[3 n2 + n1] W_P2^(n2 k2)          (three P2-point DFTs)
+//   X[k2 + P2 k1] = sum_n1 (W_P^(n1 k2) T_n1[k2]) W_3^(n1 k1)
+// with W_n = exp(DIR j 2 pi / n). Every input goes to registers first (the
+// buffer may hold the input), then sub-transform n1 runs in the n1-th third
+// of the buffer (pad(k2 + P2 k1) = k1 lds_elems(P2) + pad(k2), since P2 is a
+// multiple of 32), and the combination reads the three values of its bins
+// into registers before the outputs are stored (a store functor may write
+// anywhere in the buffer). Same functor contract as fft_run.
+template <int NT, int P, int DIR, class Load, class Store>
+__device__ __forceinline__ void fft_run3(float2* buf, int tid, Load& load, Store& store, const float2* twb) {
+  constexpr int P2 = P / 3, S1 = tri_s1<NT, P2>(), J = tri_j<NT, P2>(), LE = lds_elems(P2);
+  static_assert(3 * S1 <= 16 && 3 * J <= 16, "at most 16 values per thread");
+  static_assert(P2 % 32 == 0, "sub-transforms align with the LDS padding");
+  asm volatile("" : "+v"(tid));
+  load.prefetch(tid);
+  store.prefetch(tid);
+  float2 x[3][S1];
+#pragma unroll
+  for (int n1 = 0; n1 < 3; ++n1)
+#pragma unroll
+    for (int q = 0; q < S1; ++q) {
+      int i, b;
+      if (first_pos<NT, P, 0>(n1 * S1 + q, tid, i, b)) x[n1][q] = load(n1 * S1 + q, i, b, pad(i));
+    }
+  group_sync<NT>();
+#pragma unroll
+  for (int n1 = 0; n1 < 3; ++n1) {
+    LoadRegs<S1> lr;
+    lr.x = x[n1];
+    StoreRegion sr;
+    sr.buf = buf + n1 * LE;
+    fft_run<NT, P2, 0, DIR, kTriRM>(buf + n1 * LE, tid, lr, sr, twb);
+  }
+  group_sync<NT>();
+  const float2* tw3 = twb + twb_total();
+  float2 v[J][3];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int k2 = tid + j * NT;
+    if (P2 % NT == 0 || k2 < P2) {
+      const int p = pad(k2);
+      v[j][0] = buf[p];
+      v[j][1] = buf[LE + p];
+      v[j][2] = buf[2 * LE + p];
+    }
+  }
+  group_sync<NT>();
+  constexpr float h3 = 0.86602540378443864676f;       // sin(2 pi / 3)
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int k2 = tid + j * NT;
+    if (P2 % NT == 0 || k2 < P2) {
+      const float2 w1 = tw3[k2 * (kTw3N / P)], w2 = tw3[2 * k2 * (kTw3N / P)];
+      const float2 a = v[j][0];
+      const float2 b = cmul(v[j][1], make_float2(w1.x, DIR > 0 ? -w1.y : w1.y));
+      const float2 c = cmul(v[j][2], make_float2(w2.x, DIR > 0 ? -w2.y : w2.y));
+      // W_3 = -1/2 + DIR j sin(2 pi/3): X1 = m + d, X2 = m - d
+      const float2 sbc = cadd(b, c);
+      const float2 m = make_float2(a.x - 0.5f * sbc.x, a.y - 0.5f * sbc.y);
+      const float2 d = cscale(mulj<DIR>(csub(b, c)), h3);
+      store(3 * j, k2, cadd(a, sbc), pad(k2));
+      store(3 * j + 1, k2 + P2, cadd(m, d), LE + pad(k2));
+      store(3 * j + 2, k2 + 2 * P2, csub(m, d), 2 * LE + pad(k2));
+    }
+  }
+}
 
 // ------------------------------------------------------------------- I/O --
 // Interleaved I/Q storage; element pointers are formed once per block from the
@@ -491,7 +616,7 @@ struct StoreScaled : NoPrefetch {
 template <int L> struct LoadCyclic : NoPrefetch {
   const float2* x; int lo, hi, shift;
   __device__ __forceinline__ float2 operator()(int, int i, int, int) const {
-    return (i >= lo && i < hi) ? x[pad((i + shift) & (L - 1))] : make_float2(0.f, 0.f);
+    return (i >= lo && i < hi) ? x[pad(wrap(i + shift, L))] : make_float2(0.f, 0.f);
   }
 };
 
@@ -506,6 +631,7 @@ struct LoadLds : NoPrefetch {
 // block phase. The weights of this thread's output bins are fetched when the
 // transform starts.
 template <int NT, int L, int RM = 16> struct StoreBand {
+  static_assert(is_pow2c(L), "the pruned long IFFT takes power-of-two sizes");
   float2* V; const float* D; float2 ph; int c;
   float d[16];
   __device__ __forceinline__ void prefetch(int tid) {
@@ -547,8 +673,8 @@ template <int NT, int L, int LOGI, int RM> struct LoadPruned {
 template <int N> struct StoreAddLong : NoPrefetch {
   float2* S; const float* D; float2 ph; int L, q0;
   __device__ __forceinline__ void operator()(int, int u, float2 v, int) const {
-    const int p = (u + (L >> 1)) & (L - 1);
-    const int q = (q0 + p) & (N - 1);
+    const int p = wrap(u + (L >> 1), L);
+    const int q = wrap(q0 + p, N);
     S[q] = cadd(S[q], cscale(cmul(v, ph), D[p]));
   }
 };
@@ -626,7 +752,7 @@ template <int IO> struct LoadHigh : NoPrefetch {
 template <int NT, int L> struct LoadCompact : NoPrefetch {
   const float2* R; const float* D; float2 ph;
   __device__ __forceinline__ float2 operator()(int, int u, int, int up) const {
-    return cscale(cmul(R[up], ph), D[(u + (L >> 1)) & (L - 1)]);
+    return cscale(cmul(R[up], ph), D[wrap(u + (L >> 1), L)]);
   }
 };
 
@@ -816,7 +942,7 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
     for (int i = tid; i < NL; i += kThreads) S[i] = make_float2(0.f, 0.f);
     auto run_size = [&](auto lc) {
       constexpr int LL = decltype(lc)::value;
-      if constexpr (LL <= NL) {
+      if constexpr (divides_pow2(LL, NL)) {
         for (int m = 0; m < G.n_sb; ++m) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL) continue;
@@ -844,7 +970,7 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
     };
     run_size(SizeC<4096>()); run_size(SizeC<2048>()); run_size(SizeC<1024>()); run_size(SizeC<512>());
     run_size(SizeC<256>()); run_size(SizeC<128>()); run_size(SizeC<64>()); run_size(SizeC<32>());
-    run_size(SizeC<16>());
+    run_size(SizeC<16>()); run_size(SizeC<3072>()); run_size(SizeC<1536>()); run_size(SizeC<768>());
     __syncthreads();
     LoadLds ls;
     ls.s = S;
@@ -907,7 +1033,7 @@ __global__ __launch_bounds__(kThreads, IO == IO_C64 ? 3 : 4) void fc_rx_kernel(L
     __syncthreads();
     auto run_wave = [&](auto lc) {
       constexpr int LL = decltype(lc)::value;
-      if constexpr (LL <= NL) {
+      if constexpr (divides_pow2(LL, NL)) {
         for (int m = 0; m < G.n_sb; ++m) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave != wave) continue;
@@ -921,10 +1047,10 @@ __global__ __launch_bounds__(kThreads, IO == IO_C64 ? 3 : 4) void fc_rx_kernel(L
       }
     };
     run_wave(SizeC<1024>()); run_wave(SizeC<512>()); run_wave(SizeC<256>()); run_wave(SizeC<128>());
-    run_wave(SizeC<64>()); run_wave(SizeC<32>()); run_wave(SizeC<16>());
+    run_wave(SizeC<64>()); run_wave(SizeC<32>()); run_wave(SizeC<16>()); run_wave(SizeC<768>());
     auto run_group = [&](auto lc) {
       constexpr int LL = decltype(lc)::value;
-      if constexpr (LL <= NL) {
+      if constexpr (divides_pow2(LL, NL)) {
         for (int m = 0; m < G.n_sb; ++m) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave >= 0) continue;
@@ -941,6 +1067,8 @@ __global__ __launch_bounds__(kThreads, IO == IO_C64 ? 3 : 4) void fc_rx_kernel(L
     if (G.n_long_sb > 0) {
       run_group(SizeC<2048>());
       run_group(SizeC<4096>());
+      run_group(SizeC<1536>());
+      run_group(SizeC<3072>());
     }
   }
 }
@@ -961,7 +1089,7 @@ template <int NT, int L, int RM> struct LoadV {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       int u, b;
-      if (first_pos<NT, L, 0, RM>(s, tid, u, b)) d[s] = D[(u + (L >> 1)) & (L - 1)];
+      if (first_pos<NT, L, 0, RM>(s, tid, u, b)) d[s] = D[wrap(u + (L >> 1), L)];
     }
   }
   __device__ __forceinline__ float2 operator()(int slot, int u, int, int up) const {
@@ -994,7 +1122,7 @@ template <int IO, int NT, int L, int RM> struct StoreSubcarriers {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int u = last_pos<NT, L, 0, RM>(s, tid);
-      if (u >= 0) d[s] = D[(u + (L >> 1)) & (L - 1)];
+      if (u >= 0) d[s] = D[wrap(u + (L >> 1), L)];
     }
   }
   __device__ __forceinline__ void operator()(int slot, int u, float2 v, int up) const {
@@ -1053,7 +1181,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
       float2* A = Ab + Sb.cofs;
       for (int u = Sb.wave >= 0 ? lane : tid; u < Sb.L; u += step) {
         const int up = pad(u);
-        A[up] = rot_j(cscale(cmul(R[up], ph), D[(u + (Sb.L >> 1)) & (Sb.L - 1)]), u & 3);
+        A[up] = rot_j(cscale(cmul(R[up], ph), D[wrap(u + (Sb.L >> 1), Sb.L)]), u & 3);
       }
     }
     __syncthreads();
@@ -1066,7 +1194,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
     __syncthreads();
     auto run_wave = [&](auto lc) {
       constexpr int LL = decltype(lc)::value;
-      if constexpr (LL <= NL) {
+      if constexpr (divides_pow2(LL, NL)) {
         for (int m = 0; m < G.n_sb; ++m) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave != wave) continue;
@@ -1090,10 +1218,10 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
       }
     };
     run_wave(SizeC<1024>()); run_wave(SizeC<512>()); run_wave(SizeC<256>()); run_wave(SizeC<128>());
-    run_wave(SizeC<64>()); run_wave(SizeC<32>()); run_wave(SizeC<16>());
+    run_wave(SizeC<64>()); run_wave(SizeC<32>()); run_wave(SizeC<16>()); run_wave(SizeC<768>());
     auto run_group = [&](auto lc) {
       constexpr int LL = decltype(lc)::value;
-      if constexpr (LL <= NL) {
+      if constexpr (divides_pow2(LL, NL)) {
         for (int m = 0; m < G.n_sb; ++m) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave >= 0) continue;
@@ -1120,6 +1248,8 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
     if (G.n_long_sb > 0) {
       run_group(SizeC<2048>());
       run_group(SizeC<4096>());
+      run_group(SizeC<1536>());
+      run_group(SizeC<3072>());
     }
   }
 }
@@ -1207,12 +1337,12 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
         const BlockSb Z = a.bsb[a.blk[T.blk_first + g0 + wave].bs];
         auto issue = [&](auto lc) {
           constexpr int LL = decltype(lc)::value;
-          if constexpr (LL <= NL) {
+          if constexpr (divides_pow2(LL, NL)) {
             if (L == LL) lx.template issue_sized<LL, wave_radix_cap(LL)>(at<IO>(a.in2, Z.x0), Z.lo, Z.hi, lane);
           }
         };
         issue(SizeC<1024>()); issue(SizeC<512>()); issue(SizeC<256>()); issue(SizeC<128>());
-        issue(SizeC<64>()); issue(SizeC<32>()); issue(SizeC<16>());
+        issue(SizeC<64>()); issue(SizeC<32>()); issue(SizeC<16>()); issue(SizeC<768>());
       }
       for (int k = 0; k < nb; ++k) {
         StoreScatter sc;
@@ -1229,14 +1359,14 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
         const BlockSb Z = a.bsb[a.blk[T.blk_first + g0 + wave].bs];
         auto run = [&](auto lc) {
           constexpr int LL = decltype(lc)::value;
-          if constexpr (LL <= NL) {
+          if constexpr (divides_pow2(LL, NL)) {
             if (L != LL) return;
             sg.R = reg + wave * le; sg.ph = make_float2(Z.ph.x, Z.ph.y);
             fft_run<64, LL, 0, -1, wave_radix_cap(LL)>(sbuf + wave * le, lane, lx, sg, tw);
           }
         };
         run(SizeC<1024>()); run(SizeC<512>()); run(SizeC<256>()); run(SizeC<128>());
-        run(SizeC<64>()); run(SizeC<32>()); run(SizeC<16>());
+        run(SizeC<64>()); run(SizeC<32>()); run(SizeC<16>()); run(SizeC<768>());
       }
     }
     __syncthreads();
@@ -1246,7 +1376,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
     if (wave < NBG) {
       auto put = [&](auto lc) {
         constexpr int LL = decltype(lc)::value;
-        if constexpr (LL <= NL) {
+        if constexpr (divides_pow2(LL, NL)) {
           if (L != LL) return;
 #pragma unroll
           for (int s = 0; s < 16; ++s) {
@@ -1256,14 +1386,14 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
         }
       };
       put(SizeC<1024>()); put(SizeC<512>()); put(SizeC<256>()); put(SizeC<128>());
-      put(SizeC<64>()); put(SizeC<32>()); put(SizeC<16>());
+      put(SizeC<64>()); put(SizeC<32>()); put(SizeC<16>()); put(SizeC<768>());
     }
     __syncthreads();
     float* part = a.part + T.part_off + Sb.aofs;
     for (int u = tid; u < L; u += kThreads) {
       float sum = 0.f;
       for (int w = 0; w < NBG; ++w) sum += red[w * L + u];
-      part[(u + (L >> 1)) & (L - 1)] = sum;
+      part[wrap(u + (L >> 1), L)] = sum;
     }
     return;
   }
@@ -1275,7 +1405,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
     const SbDesc Sb = a.sb[G.sb_first];
     auto run = [&](auto lc) {
       constexpr int LL = decltype(lc)::value;
-      if constexpr (LL <= NL && LL > 1024) {
+      if constexpr (divides_pow2(LL, NL) && LL > 1024) {
         if (Sb.L != LL) return;
         constexpr int RML = radix_cap(LL);
         StoreGradReg sg;
@@ -1301,11 +1431,11 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
           const int u = last_pos<kThreads, LL, 0, RML>(s, tid);
-          if (u >= 0) part[(u + (LL >> 1)) & (LL - 1)] = sg.r[s];
+          if (u >= 0) part[wrap(u + (LL >> 1), LL)] = sg.r[s];
         }
       }
     };
-    run(SizeC<2048>()); run(SizeC<4096>());
+    run(SizeC<2048>()); run(SizeC<4096>()); run(SizeC<1536>()); run(SizeC<3072>());
     return;
   }
   for (int i = tid; i < G.acc_len; i += kThreads) acc[i] = 0.f;
@@ -1322,7 +1452,7 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
     __syncthreads();
     auto run_wave = [&](auto lc) {
       constexpr int LL = decltype(lc)::value;
-      if constexpr (LL <= NL) {
+      if constexpr (divides_pow2(LL, NL)) {
         for (int m = 0; m < G.n_sb; ++m) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave != wave) continue;
@@ -1337,10 +1467,10 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
       }
     };
     run_wave(SizeC<1024>()); run_wave(SizeC<512>()); run_wave(SizeC<256>()); run_wave(SizeC<128>());
-    run_wave(SizeC<64>()); run_wave(SizeC<32>()); run_wave(SizeC<16>());
+    run_wave(SizeC<64>()); run_wave(SizeC<32>()); run_wave(SizeC<16>()); run_wave(SizeC<768>());
     auto run_group = [&](auto lc) {
       constexpr int LL = decltype(lc)::value;
-      if constexpr (LL <= NL) {
+      if constexpr (divides_pow2(LL, NL)) {
         for (int m = 0; m < G.n_sb; ++m) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave >= 0) continue;
@@ -1357,13 +1487,15 @@ __global__ __launch_bounds__(kThreads) void fc_wgrad_kernel(LaunchArgs a, int) {
     if (G.n_long_sb > 0) {
       run_group(SizeC<2048>());
       run_group(SizeC<4096>());
+      run_group(SizeC<1536>());
+      run_group(SizeC<3072>());
     }
   }
   __syncthreads();
   float* part = a.part + T.part_off;
   for (int m = 0; m < G.n_sb; ++m) {
     const SbDesc Sb = a.sb[G.sb_first + m];
-    for (int u = tid; u < Sb.L; u += kThreads) part[Sb.aofs + ((u + (Sb.L >> 1)) & (Sb.L - 1))] = acc[Sb.aofs + u];
+    for (int u = tid; u < Sb.L; u += kThreads) part[Sb.aofs + wrap(u + (Sb.L >> 1), Sb.L)] = acc[Sb.aofs + u];
   }
 }
 
@@ -1424,7 +1556,10 @@ hipError_t launch_pruned(const LaunchArgs& a, int logi, size_t lds, hipStream_t 
 template <int IO, int SZ>
 hipError_t launch_size(int cls, const LaunchArgs& a, int aux, size_t lds, hipStream_t s, dim3 grid) {
   dim3 block(kThreads);
-  if (cls == 0) return launch_pruned<IO, SZ>(a, aux, lds, s, grid);
+  if (cls == 0) {
+    if constexpr (is_pow2c(SZ)) return launch_pruned<IO, SZ>(a, aux, lds, s, grid);
+    else return hipErrorInvalidValue;        // mixed-radix groups use the full-transform kernel
+  }
   if (cls == 1) {
     if (a.front) hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ, true>), grid, block, lds, s, a, aux);
     else hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ, false>), grid, block, lds, s, a, aux);
@@ -1450,6 +1585,7 @@ hipError_t launch_io(int cls, int size, const LaunchArgs& a, int aux, size_t lds
   switch (size) {
 #define FC_SZ(SZ) case SZ: return launch_size<IO, SZ>(cls, a, aux, lds, s, grid);
     FC_SZ(16) FC_SZ(32) FC_SZ(64) FC_SZ(128) FC_SZ(256) FC_SZ(512) FC_SZ(1024) FC_SZ(2048) FC_SZ(4096)
+    FC_SZ(768) FC_SZ(1536) FC_SZ(3072)
 #undef FC_SZ
     default: return hipErrorInvalidValue;
   }
@@ -1485,7 +1621,7 @@ hipError_t lds_limits_io(size_t bytes) {
   hipError_t e = hipSuccess;
 #define FC_SZ(SZ)                                                                                   \
   {                                                                                                 \
-    hipError_t r1 = lds_limit_pruned<IO, SZ>(bytes);                                                \
+    hipError_t r1 = is_pow2c(SZ) ? lds_limit_pruned<IO, is_pow2c(SZ) ? SZ : 16>(bytes) : hipSuccess;   \
     hipError_t r2 = hipFuncSetAttribute((const void*)fc_tx_full_kernel<IO, SZ, false>,              \
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
     hipError_t r2f = hipFuncSetAttribute((const void*)fc_tx_full_kernel<IO, SZ, true>,              \
@@ -1504,6 +1640,7 @@ hipError_t lds_limits_io(size_t bytes) {
     if (r4 != hipSuccess) e = r4;                                                                   \
   }
   FC_SZ(16) FC_SZ(32) FC_SZ(64) FC_SZ(128) FC_SZ(256) FC_SZ(512) FC_SZ(1024) FC_SZ(2048) FC_SZ(4096)
+  FC_SZ(768) FC_SZ(1536) FC_SZ(3072)
 #undef FC_SZ
   return e;
 }

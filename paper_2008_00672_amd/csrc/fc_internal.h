@@ -18,6 +18,19 @@ enum IoType : int32_t { IO_C64 = 0, IO_F16 = 1, IO_BF16 = 2 };
 // the device code's pad()).
 constexpr int lds_elems(int n) { return n + (n >> 5); }
 
+// Transform sizes: powers of two 16..4096, and the mixed-radix sizes
+// 3 x 2^k for 768..3072 (three decimated 2^k-point transforms and a radix-3
+// combination; the paper's example of a short transform of 768 = 3 x 256
+// points, Sec. VI-C). Interpolation factors n_long / n_short are powers of two.
+constexpr bool is_pow2c(int v) { return v > 0 && (v & (v - 1)) == 0; }
+constexpr bool is_tri(int P) { return P % 3 == 0 && is_pow2c(P / 3) && P >= 768 && P <= 3072; }
+constexpr bool fft_size_ok(int P) { return (is_pow2c(P) && P >= 16 && P <= kMaxPoints) || is_tri(P); }
+// entries of the radix-3 combination's twiddle table exp(-j 2 pi k / 3072),
+// stored after the per-pass twiddle bases (every 3 x 2^k size divides 3072)
+constexpr int kTw3N = 3072;
+// a group of long size N holds subbands of size L when N / L is an integral power of two
+constexpr bool divides_pow2(int L, int N) { return L <= N && N % L == 0 && is_pow2c(N / L); }
+
 // TX pruned kernel. Short FFTs one per wave (blocks in groups, one band
 // region each) for L < 256 and for N <= 1024; otherwise on the whole
 // workgroup in the long IFFT buffer, one block at a time: that frees the

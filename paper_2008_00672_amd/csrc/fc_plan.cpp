@@ -164,9 +164,11 @@ fc_status analyse(const fc_subband& d, Sub& s) {
   int ratio = d.scs_khz / 15;
   if (!is_pow2(ratio)) return FC_E_ARG;
   s.mu = ilog2(ratio);
-  if (!is_pow2(d.n_short) || !is_pow2(d.n_long)) return FC_E_UNSUPPORTED;
-  if (d.n_short < 16 || d.n_long > kMaxPoints) return FC_E_UNSUPPORTED;
+  // powers of two 16..4096 or 3 x 2^k for 768..3072, with n_long / n_short a
+  // power of two (the interpolation factor)
+  if (!fft_size_ok(d.n_short) || !fft_size_ok(d.n_long)) return FC_E_UNSUPPORTED;
   if (d.n_long < d.n_short) return FC_E_SHAPE;
+  if (!divides_pow2(d.n_short, d.n_long)) return FC_E_SHAPE;
   if (d.n_active + 2 * d.n_tb > d.n_short) return FC_E_SHAPE;
   if (std::abs((int64_t)d.center_bin) + d.n_short / 2 > d.n_long / 2) return FC_E_SHAPE;
   if (d.overlap_den <= 0 || d.overlap_num <= 0 || 2 * d.overlap_num > d.overlap_den) return FC_E_UNSUPPORTED;
@@ -290,7 +292,7 @@ void build_op(fc_plan* P, int op_index) {
       const Sub& s = P->subs[m];
       const int q0 = (int)imod((int64_t)s.d.center_bin - s.L / 2, s.N);
       bool over = acc + lds_elems(s.L) > kRxMaxLds;
-      for (int p = 0; p < s.L && !over; ++p) over = mult[(q0 + p) & (G.N - 1)] >= kRxMaxDest;
+      for (int p = 0; p < s.L && !over; ++p) over = mult[(q0 + p) % G.N] >= kRxMaxDest;
       if (!cur.subs.empty() && over) {
         ogroups.push_back(cur);
         cur.subs.clear();
@@ -299,7 +301,7 @@ void build_op(fc_plan* P, int op_index) {
       }
       cur.subs.push_back(m);
       acc += lds_elems(s.L);
-      for (int p = 0; p < s.L; ++p) mult[(q0 + p) & (G.N - 1)]++;
+      for (int p = 0; p < s.L; ++p) mult[(q0 + p) % G.N]++;
     }
     ogroups.push_back(cur);
   }
@@ -313,7 +315,8 @@ void build_op(fc_plan* P, int op_index) {
     const Sub& s0 = P->subs[OG.subs[0]];
     // tapered output windows are applied by the full-transform kernel only
     gd.taper = tk == 0 ? G.taper : 0;
-    gd.prune = (tk == 0 && OG.subs.size() == 1 && s0.I >= 2 && s0.L >= 16 && !gd.taper) ? 1 : 0;
+    // (mixed-radix sizes always take the full long transform)
+    gd.prune = (tk == 0 && OG.subs.size() == 1 && s0.I >= 2 && s0.L >= 16 && !gd.taper && is_pow2(s0.L)) ? 1 : 0;
     op.grp.push_back(gd);
     int cofs = 0;
     for (int m : OG.subs) {
@@ -338,8 +341,8 @@ void build_op(fc_plan* P, int op_index) {
       for (int i = 0; i < gr.n_sb; ++i) {
         const SbDesc& d = op.sb[gr.sb_first + i];
         for (int pidx = 0; pidx < d.L; ++pidx) {
-          const int q = (d.q0 + pidx) & (gr.N - 1);
-          const int u = (pidx + d.L / 2) & (d.L - 1);
+          const int q = (d.q0 + pidx) % gr.N;
+          const int u = (pidx + d.L / 2) % d.L;
           const uint64_t dst = (uint64_t)(d.cofs + u + (u >> 5));
           uint64_t& e = op.rxmap[gr.map_off + q];
           e &= ~(0xffffull << (16 * cnt[q]));
@@ -903,7 +906,7 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
   }
   // per-pass bases w^1, w^2, w^4, w^8 of w = exp(-j 2 pi k / (NS R)) for every
   // non-first pass of every transform size and radix plan (layout: twb_off)
-  std::vector<Cf> twp(twb_total());
+  std::vector<Cf> twp(twb_total() + kTw3N);
   for (int RM : {16, 8, 4}) {
     for (int Pn = 2; Pn <= kMaxPoints; Pn <<= 1) {
       for (int sp = 1; sp < npass(Pn, RM); ++sp) {
@@ -918,6 +921,11 @@ fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, in
         }
       }
     }
+  }
+  // radix-3 combination of the mixed-radix sizes: exp(-j 2 pi k / 3072)
+  for (int k = 0; k < kTw3N; ++k) {
+    const double a = 2.0 * kPi * k / kTw3N;
+    twp[twb_total() + k] = Cf{(float)std::cos(a), (float)-std::sin(a)};
   }
   std::vector<float> w(P->w_total);
   for (int m = 0; m < n_sb; ++m) std::copy(P->subs[m].w.begin(), P->subs[m].w.end(), w.begin() + P->w_off[m]);

@@ -462,5 +462,23 @@ ALL_PINS = {
     "brute_sync_ols": lambda fc: brute_sync_ols(fc),
     "brute_sync_ols_taper": lambda fc: brute_sync_ols(fc, taper=4),
     "taper_interior": lambda fc: taper_interior(fc),
+    # transform lengths that are not powers of two (3 x 2^k, as the paper's
+    # 768 = 3 x 256 short transform, Sec. VI-C): the same pins at L = 24
+    # (N = 96) and, for the brute-force loops, L = 12 (N = 48)
+    "pr1_sync_l24": lambda fc: pr1_sync(fc, L=24, N=96, c=7, ncp=(20, 16, 16, 20, 16)),
+    "pr1_cont_ols_l24": lambda fc: pr1_cont(fc, False, L=24, N=96),
+    "pr1_cont_ola_l24": lambda fc: pr1_cont(fc, True, L=24, N=96),
+    "tone_tx_l24": lambda fc: tone_tx(fc, L=24, N=96, c=9),
+    "tone_rx_l24": lambda fc: tone_rx(fc, L=24, N=96, c=-11),
+    "tone_rx_sync_l24": lambda fc: tone_rx_sync(fc, L=24, N=96),
+    "lin_i1_ols_l24": lambda fc: lin_i1_cont(fc, False, L=24),
+    "lin_i1_ola_l24": lambda fc: lin_i1_cont(fc, True, L=24),
+    "lin_i1_sync_l24": lambda fc: lin_i1_sync(fc, L=24),
+    "brute_ola_l12": lambda fc: brute_cont(fc, True, L=12, N=48),
+    "brute_ols_l12": lambda fc: brute_cont(fc, False, L=12, N=48),
+    "brute_sync_l12": lambda fc: brute_sync(fc, L=12, N=48),
+    "adjoint_sync_l24": lambda fc: adjoint_sync(fc, L=24, N=96),
+    "adjoint_cont_l24": lambda fc: adjoint_cont(fc, True, L=24, N=96),
+    "tone_rx_subcarriers_l24": lambda fc: tone_rx_subcarriers(fc, L=24, N=96),
 }
 TOL = 1e-10

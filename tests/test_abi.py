@@ -110,6 +110,10 @@ def test_rx_group_split(name):
 
 BAD = {
     "short_not_pow2": (dict(n_short=96), "FC_E_UNSUPPORTED"),
+    "short_3x128": (dict(n_short=384), "FC_E_UNSUPPORTED"),     # mixed radix from 768 only
+    "short_5x256": (dict(n_short=1280, n_long=2560), "FC_E_UNSUPPORTED"),
+    "interp_not_pow2": (dict(n_short=768, n_long=1024, n_active=288), "FC_E_SHAPE"),
+    "interp_three": (dict(n_short=512, n_long=1536, n_active=288), "FC_E_SHAPE"),
     "long_too_big": (dict(n_long=8192), "FC_E_UNSUPPORTED"),
     "short_gt_long": (dict(n_short=4096, n_long=2048), "FC_E_SHAPE"),
     "band_too_wide": (dict(n_active=500, n_tb=8), "FC_E_SHAPE"),
@@ -128,6 +132,20 @@ BAD = {
     "taper_past_leading_overlap": (dict(mode="sync_ols", taper=706), "FC_E_SHAPE"),
 }
 CODES = {"FC_E_ARG": -1, "FC_E_SHAPE": -2, "FC_E_UNSUPPORTED": -3}
+
+
+@pytest.mark.parametrize("n_short,n_long", [(768, 768), (768, 1536), (768, 3072), (1536, 3072), (3072, 3072)])
+def test_mixed_radix_sizes_accepted(n_short, n_long):
+    """3 x 2^k transform lengths (768 = 3 x 256, Sec. VI-C) with a power-of-two
+    interpolation factor: the plan's layout and CP schedule follow the oracle's."""
+    fc = _lib()
+    s = W.subband(15, 14, 600, 8, n_short, n_long, 0, "sync_ola")
+    p = fc.Plan([s], device=-1)
+    _, lens, P = stream_offsets([s])
+    lo, hi = p.layout(fc.OP_TX)
+    assert hi[-1] == lens[0] and lo[-1] == P[0]["n_in"]
+    assert list(p.symbols(0)[0]) == P[0]["ncp"]
+    assert p.stats(fc.OP_TX)["blocks"] == 28
 
 
 @pytest.mark.parametrize("case", sorted(BAD))

@@ -30,9 +30,9 @@ OOB_GUARD = 8          # bins excluded on each side of the transition bands
 
 
 class Setup:
-    def __init__(self):
-        self.sb = {m: W.wideband_slot(m)[0][0] for m in ("cont_ols", "sync_ola")}
-        self.meta = W.wideband_slot("cont_ols")[1]
+    def __init__(self, n=1024):
+        self.sb = {m: W.wideband_slot(m, n)[0][0] for m in ("cont_ols", "sync_ola")}
+        self.meta = W.wideband_slot("cont_ols", n)[1]
         self.pc, self.ps = sub_params(self.sb["cont_ols"]), sub_params(self.sb["sync_ola"])
         xs, Ds, grids = make_inputs([self.sb["cont_ols"]], self.meta["qam"], self.meta["seed"])
         self.x, self.D, self.grid = xs[0], Ds[0], grids[0]

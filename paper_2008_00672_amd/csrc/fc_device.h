@@ -202,12 +202,15 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const TwB& t) {
 }
 
 // Mixed-radix transforms of P = 3 P2 points (is_tri(P)): three decimated
-// P2-point sub-transforms, each with the radix-4 plan, then a radix-3
-// combination (fft_run3). Per thread: S1 first-pass slots of each
-// sub-transform, and up to four output bins k2 (each giving three outputs).
+// P2-point sub-transforms, then a radix-3 combination (fft_run3). On one
+// wave the sub-transforms run one after the other with the radix-4 plan
+// (per thread S1 first-pass slots of each); on a workgroup waves 0..2 run
+// one sub-transform each with the one-wave plan (per thread the P2 / 64
+// first-pass slots of its wave's sub-transform). Per thread up to four
+// output bins k2 of the combination (each giving three outputs).
 constexpr int kTriRM = 4;
 template <int NT, int P2>
-constexpr int tri_s1() { return (((P2 / 4) + NT - 1) / NT) * 4; }
+constexpr int tri_s1() { return NT == kThreads ? P2 / 64 : (((P2 / 4) + NT - 1) / NT) * 4; }
 template <int NT, int P2>
 constexpr int tri_j() { return (P2 + NT - 1) / NT; }
 
@@ -222,9 +225,14 @@ __device__ __forceinline__ bool first_pos(int s, int tid, int& i, int& b) {
   if constexpr (is_tri(P)) {
     static_assert(LOGBT == 0, "mixed-radix transforms are not interleaved");
     constexpr int P2 = P / 3, S1 = tri_s1<NT, P2>();
-    const int n1 = s / S1;
-    int i2;
-    if (n1 >= 3 || !first_pos<NT, P2, 0, kTriRM>(s - n1 * S1, tid, i2, b)) return false;
+    int n1, i2;
+    if constexpr (NT == kThreads) {          // wave n1 holds sub-transform n1
+      n1 = tid >> 6;
+      if (n1 >= 3 || !first_pos<64, P2, 0, wave_radix_cap(P2)>(s, tid & 63, i2, b)) return false;
+    } else {
+      n1 = s / S1;
+      if (n1 >= 3 || !first_pos<NT, P2, 0, kTriRM>(s - n1 * S1, tid, i2, b)) return false;
+    }
     i = 3 * i2 + n1;
     return true;
   }
@@ -423,30 +431,44 @@ struct StoreRegion : NoPrefetch {
 template <int NT, int P, int DIR, class Load, class Store>
 __device__ __forceinline__ void fft_run3(float2* buf, int tid, Load& load, Store& store, const float2* twb) {
   constexpr int P2 = P / 3, S1 = tri_s1<NT, P2>(), J = tri_j<NT, P2>(), LE = lds_elems(P2);
-  static_assert(3 * S1 <= 16 && 3 * J <= 16, "at most 16 values per thread");
+  constexpr bool kWaves = NT == kThreads;           // one sub-transform per wave
+  constexpr int NSUB = kWaves ? 1 : 3;               // sub-transforms loaded by each thread
+  static_assert(NSUB * S1 <= 16 && 3 * J <= 16, "at most 16 values per thread");
   static_assert(P2 % 32 == 0, "sub-transforms align with the LDS padding");
   asm volatile("" : "+v"(tid));
   load.prefetch(tid);
   store.prefetch(tid);
-  float2 x[3][S1];
+  float2 x[NSUB][S1];
 #pragma unroll
-  for (int n1 = 0; n1 < 3; ++n1)
+  for (int n1 = 0; n1 < NSUB; ++n1)
 #pragma unroll
     for (int q = 0; q < S1; ++q) {
       int i, b;
       if (first_pos<NT, P, 0>(n1 * S1 + q, tid, i, b)) x[n1][q] = load(n1 * S1 + q, i, b, pad(i));
     }
   group_sync<NT>();
+  if constexpr (kWaves) {
+    const int w = tid >> 6;
+    if (w < 3) {
+      LoadRegs<S1> lr;
+      lr.x = x[0];
+      StoreRegion sr;
+      sr.buf = buf + w * LE;
+      fft_run<64, P2, 0, DIR, wave_radix_cap(P2)>(buf + w * LE, tid & 63, lr, sr, twb);
+    }
+  } else {
 #pragma unroll
-  for (int n1 = 0; n1 < 3; ++n1) {
-    LoadRegs<S1> lr;
-    lr.x = x[n1];
-    StoreRegion sr;
-    sr.buf = buf + n1 * LE;
-    fft_run<NT, P2, 0, DIR, kTriRM>(buf + n1 * LE, tid, lr, sr, twb);
+    for (int n1 = 0; n1 < 3; ++n1) {
+      LoadRegs<S1> lr;
+      lr.x = x[n1];
+      StoreRegion sr;
+      sr.buf = buf + n1 * LE;
+      fft_run<NT, P2, 0, DIR, kTriRM>(buf + n1 * LE, tid, lr, sr, twb);
+    }
   }
   group_sync<NT>();
-  const float2* tw3 = twb + twb_total();
+  constexpr int kTw3Off = twb_total();                // folded here, not evaluated per call
+  const float2* tw3 = twb + kTw3Off;
   float2 v[J][3];
 #pragma unroll
   for (int j = 0; j < J; ++j) {

@@ -98,6 +98,9 @@ class TxObjective:
                 raise ValueError("one subband per stream expected")
             groups.setdefault((s["n_long"], tuple(int(v) for v in ncp)), []).append(k)
         self.n = len(sbs)
+        # streams in order (one subband each): y splits into them in one view
+        self.stream_lens = [int(v) for v in np.diff(hi)]
+        self.stream_of = [s["stream"] for s in sbs]
         self.groups = []
         for (N, ncp), ks in groups.items():
             ncp = np.array(ncp)
@@ -123,7 +126,6 @@ class TxObjective:
                 # + 2 pi kb d_m / N (the window's cyclic shift) - 2 pi c t0_m / N
                 # (carrier phase at the useful part's start), integer-reduced
                 ph[g, :, :K] = 2 * np.pi * ((np.outer(d, kb) - c * t0[:, None]) % N) / N
-            first = np.array([int(hi[sbs[k]["stream"]]) for k in ks])
             # the symbols' windows do not overlap (each starts at most half a
             # CP before its useful part): the output splits into windows and
             # the gaps between them
@@ -132,7 +134,7 @@ class TxObjective:
             if min(pieces) < 0:
                 raise ValueError("symbol windows overlap")
             self.groups.append(dict(
-                N=N, ks=torch.tensor(ks, device=dev), first=[int(v) for v in first], Q=Q, pieces=pieces,
+                N=N, ks=torch.tensor(ks, device=dev), ks_list=list(ks), Q=Q, pieces=pieces,
                 bins=torch.tensor(bins, device=dev)[:, None, :].expand(len(ks), B, Kmax),
                 mask=torch.tensor(mask, device=dev)[:, None, :],
                 qam=torch.tensor(qam, dtype=dtype, device=dev),
@@ -145,9 +147,13 @@ class TxObjective:
         y = y.to(self.dtype)
         evm = y.new_zeros(self.n, dtype=y.real.dtype)
         oob = y.new_zeros(self.n, dtype=y.real.dtype)
+        # one split of the output into its streams (its backward is a single
+        # concatenation, where slicing per subband would build a full-size
+        # gradient per slice)
+        streams = torch.split(y, self.stream_lens)
         for G in self.groups:
             N = G["N"]
-            Y = torch.stack([y[a:a + G["Q"]] for a in G["first"]])     # (n_g, Q)
+            Y = torch.stack([streams[self.stream_of[k]] for k in G["ks_list"]])   # (n_g, Q)
             W = torch.stack(torch.split(Y, G["pieces"], dim=1)[1::2], dim=1)   # (n_g, B, N) symbol windows
             Z = torch.fft.fft(W, dim=-1)
             Z = torch.gather(Z, 2, G["bins"]) * G["phase"]              # active subcarriers

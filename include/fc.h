@@ -336,7 +336,7 @@ fc_status fc_plan_stats(const fc_plan* plan, int32_t op, int64_t* n_blocks, int6
  *   conc     1..4: how many launches of one independent set (kernel classes
  *            writing disjoint outputs) may run at once, on the caller's
  *            stream plus side streams owned by the plan.
- * Results do not depend on the tuning (same arithmetic per block).
+ * Results do not depend on run_len or conc (same arithmetic per block).
  * fc_plan_set_tuning waits for the plan's device to go idle and rebuilds the
  * op's work tables (freeing the old ones): graphs captured before hold the
  * old tables' addresses and must be captured again. Errors: FC_E_ARG (out
@@ -347,10 +347,28 @@ fc_status fc_plan_set_tuning(fc_plan* plan, int32_t op, int32_t run_len, int32_t
 fc_status fc_plan_get_tuning(const fc_plan* plan, int32_t op, int32_t* run_len, int32_t* conc);
 
 /*
+ * Transform plan of operation op (FC_OP_TX .. FC_OP_TXG), 0 (default) or 1,
+ * a choice between precompiled kernels: for the TX operations, the other
+ * placement of the short FFTs of single-subband groups with a pruned long
+ * IFFT and n_short <= 1024 (one wave per block, blocks in groups, against
+ * the whole workgroup, one block at a time); for FC_OP_RX, FC_OP_ADJ and
+ * FC_OP_RXD, the long FFT with the next lower radix (radix-8 passes at
+ * n_long = 4096, radix 4 at 2048). Elsewhere both plans are the same kernel.
+ * Plan 1 changes the order of the FP32 operations, so results differ from
+ * plan 0 by rounding. Set like fc_plan_set_tuning (device idle, tables
+ * rebuilt, graphs must be captured again); fc_plan_autotune also chooses it.
+ * Errors: FC_E_ARG (op or plan out of range), FC_E_STATE, FC_E_NOMEM,
+ * FC_E_DEVICE.
+ */
+fc_status fc_plan_set_transform_plan(fc_plan* plan, int32_t op, int32_t tplan);
+fc_status fc_plan_get_transform_plan(const fc_plan* plan, int32_t op, int32_t* tplan);
+
+/*
  * Autotuner: times op on the caller's buffers (in / out as for the op's
  * call; out is overwritten) for run_len in {0, 8, 16, 32, 64} (TX) or
  * {0, 1, 2, 4, 8, 16} (RX, adjoint; {0, 2, 4, 8, 16} demodulating RX) and
- * conc in {1, 4}, one warm-up and six timed calls each (HIP events on
+ * conc in {1, 4}, and the transform plans 0 and 1 where they differ for
+ * this op (fc_plan_set_transform_plan), one warm-up and six timed calls each (HIP events on
  * `stream`, minimum kept; on a stream other than the legacy null stream the
  * call is captured once as a HIP graph and the replays are timed, so host
  * launch gaps do not enter the choice), then applies the
@@ -358,7 +376,8 @@ fc_status fc_plan_get_tuning(const fc_plan* plan, int32_t op, int32_t* run_len, 
  * own and spreads the launches over the streams longest first by those
  * measured times (kept until the next fc_plan_set_tuning). Synchronous. The
  * chosen values and time per call (ms) are written to the non-NULL result
- * pointers.
+ * pointers; the chosen transform plan is read back with
+ * fc_plan_get_transform_plan.
  */
 fc_status fc_plan_autotune(fc_plan* plan, int32_t op, const void* in, void* out, void* stream,
                            int32_t* best_run_len, int32_t* best_conc, float* best_ms);

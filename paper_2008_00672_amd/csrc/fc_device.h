@@ -769,12 +769,23 @@ template <int IO> struct LoadHigh : NoPrefetch {
 // RX short IFFT first pass from the subband's compacted region (bin u of the
 // subband at region[pad(u)], already in inverse-shift order), weighted by
 // D[p] and the conj phase; the transform then runs in place in the region.
-// (The weights are read when used: fetched ahead they would hold 16 registers
-// through the transform and push the RX kernel past four waves per SIMD.)
-template <int NT, int L> struct LoadCompact : NoPrefetch {
+// The weights of this thread's first-pass bins are fetched when the transform
+// starts, together with its twiddle bases (their registers live only until
+// the first pass: the RX kernel keeps four waves per SIMD; 2 % off the RX
+// call against reading them at use).
+template <int NT, int L> struct LoadCompact {
   const float2* R; const float* D; float2 ph;
-  __device__ __forceinline__ float2 operator()(int, int u, int, int up) const {
-    return cscale(cmul(R[up], ph), D[wrap(u + (L >> 1), L)]);
+  float d[16];
+  __device__ __forceinline__ void prefetch(int tid) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      int u, b;
+      if (first_pos<NT, L, 0, NT == 64 ? wave_radix_cap(L) : radix_cap(L)>(s, tid, u, b))
+        d[s] = D[wrap(u + (L >> 1), L)];
+    }
+  }
+  __device__ __forceinline__ float2 operator()(int slot, int, int, int up) const {
+    return cscale(cmul(R[up], ph), d[slot]);
   }
 };
 
@@ -837,15 +848,15 @@ __device__ __forceinline__ void zero_span(void* out, int64_t lo, int64_t hi) {
 // IFFTs and epilogues in block order (the OLA carry passes from block to
 // block through LDS). Otherwise one block at a time, the short FFT on the
 // whole workgroup in the long IFFT buffer.
-template <int IO, int L, int LOGI, bool FRONT>
-__global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI)) void fc_tx_pruned_kernel(LaunchArgs a) {
+template <int IO, int L, int LOGI, bool FRONT, int TP>
+__global__ __launch_bounds__(kThreads, pruned_waves_per_simd(L, L << LOGI, TP)) void fc_tx_pruned_kernel(LaunchArgs a) {
   constexpr int N = L << LOGI;
-  constexpr bool kWaveShort = pruned_wave_short(L, L << LOGI);
-  constexpr int NB = pruned_group_blocks(L, N);             // blocks per group
+  constexpr bool kWaveShort = pruned_ws(L, N, TP);          // transform plan TP
+  constexpr int NB = pruned_group_blocks(L, N, TP);         // blocks per group
   // the long IFFT's first-pass twiddles depend only on the thread and the
   // subband: fetched once per task and kept in registers where the LDS
   // already limits occupancy to two workgroups per CU (registers are free)
-  constexpr bool kKeepTwiddles = N <= 2048 && pruned_waves_per_simd(L, N) <= 2;
+  constexpr bool kKeepTwiddles = N <= 2048 && pruned_waves_per_simd(L, N, TP) <= 2;
   extern __shared__ float2 smem[];
   const int task = blockIdx.x;
   if (task >= a.n_task) return;
@@ -1018,8 +1029,9 @@ __global__ __launch_bounds__(kThreads) void fc_tx_full_kernel(LaunchArgs a, int 
 // four waves per SIMD (what the LDS allows at N = 4096); FP32 storage holds
 // twice the prefetched input and would spill there (40 registers, 10 %
 // slower than three waves without spills), so it takes three.
-template <int IO, int NL>
+template <int IO, int NL, int TP>
 __global__ __launch_bounds__(kThreads, IO == IO_C64 ? 3 : 4) void fc_rx_kernel(LaunchArgs a, int) {
+  constexpr int RML = rx_long_cap(NL, TP);                 // long-FFT radix plan (transform plan TP)
   extern __shared__ float2 smem[];
   // consecutive tasks (runs sharing input at their boundary) go to the same
   // XCD: the dispatcher places workgroup i on XCD i mod 8
@@ -1037,7 +1049,7 @@ __global__ __launch_bounds__(kThreads, IO == IO_C64 ? 3 : 4) void fc_rx_kernel(L
   const int wave = ((tid >> 6) + blockIdx.x) & 3;
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const uint64_t* map = a.rxmap + G.map_off;
-  LoadAhead<IO, kThreads, NL, radix_cap(NL)> lh;
+  LoadAhead<IO, kThreads, NL, RML> lh;
   {
     const BlockDesc B0 = a.blk[T.blk_first];
     lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
@@ -1047,7 +1059,7 @@ __global__ __launch_bounds__(kThreads, IO == IO_C64 ? 3 : 4) void fc_rx_kernel(L
     StoreScatter sc;
     sc.S = S; sc.map = map;
     __syncthreads();
-    fft_run<kThreads, NL, 0, -1, radix_cap(NL)>(S, tid, lh, sc, tw);
+    fft_run<kThreads, NL, 0, -1, RML>(S, tid, lh, sc, tw);
     if (bi + 1 < T.blk_count) {
       const BlockDesc Bn = a.blk[T.blk_first + bi + 1];
       lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
@@ -1162,8 +1174,9 @@ template <int IO, int NT, int L, int RM> struct StoreSubcarriers {
 // subband runs V = A - B -> IFFT -> keep the first half -> FFT -> + B in its
 // second region and writes the L subcarriers. Subbands with L <= 1024 run on
 // one wave (assignment as the RX kernel), longer ones on the workgroup.
-template <int IO, int NL>
+template <int IO, int NL, int TP>
 __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
+  constexpr int RML = rx_long_cap(NL, TP);                 // long-FFT radix plan (transform plan TP)
   extern __shared__ float2 smem[];
   const int n = gridDim.x;
   int task = blockIdx.x;
@@ -1177,7 +1190,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
   const int wave = ((tid >> 6) + blockIdx.x) & 3;
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const uint64_t* map = a.rxmap + G.map_off;
-  LoadAhead<IO, kThreads, NL, radix_cap(NL)> lh;
+  LoadAhead<IO, kThreads, NL, RML> lh;
   {
     const BlockDesc B0 = a.blk[T.blk_first];
     lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
@@ -1189,7 +1202,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
     sc.S = S; sc.map = map;
     // ---- first block: spectrum -> regions -> A
     __syncthreads();
-    fft_run<kThreads, NL, 0, -1, radix_cap(NL)>(S, tid, lh, sc, tw);
+    fft_run<kThreads, NL, 0, -1, RML>(S, tid, lh, sc, tw);
     lh.issue(at<IO>(a.in, B1.t0), B1.hlo, B1.hhi, tid);
     __syncthreads();
     for (int m = 0; m < G.n_sb; ++m) {
@@ -1208,7 +1221,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
     }
     __syncthreads();
     // ---- second block: spectrum -> regions; per subband the joint transform
-    fft_run<kThreads, NL, 0, -1, radix_cap(NL)>(S, tid, lh, sc, tw);
+    fft_run<kThreads, NL, 0, -1, RML>(S, tid, lh, sc, tw);
     if (bi + 2 < T.blk_count) {
       const BlockDesc Bn = a.blk[T.blk_first + bi + 2];
       lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
@@ -1556,17 +1569,29 @@ __global__ __launch_bounds__(kThreads) void fc_zero_kernel(void* out, int64_t n)
 // (size = N, aux = largest L), 2 = RX and adjoint (size = N), 3 = weight
 // gradient (size = N), 4 = demodulating RX (size = N), 5 = weight-gradient
 // reduction (one workgroup per group, n_task = number of groups).
+// One pruned-TX instance: transform plan a.tplan where the size has a second
+// plan (pruned_has_alt), else plan 0.
+template <int IO, int L, int LI>
+hipError_t launch_pruned_li(const LaunchArgs& a, size_t lds, hipStream_t s, dim3 grid) {
+  dim3 block(kThreads);
+  if constexpr (pruned_has_alt(L)) {
+    if (a.tplan) {
+      if (a.front) hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI, true, 1>), grid, block, lds, s, a);
+      else hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI, false, 1>), grid, block, lds, s, a);
+      return hipGetLastError();
+    }
+  }
+  if (a.front) hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI, true, 0>), grid, block, lds, s, a);
+  else hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI, false, 0>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
 template <int IO, int L>
 hipError_t launch_pruned(const LaunchArgs& a, int logi, size_t lds, hipStream_t s, dim3 grid) {
-  dim3 block(kThreads);
   switch (logi) {
 #define FC_LI(LI) \
   case LI:                                                                                          \
-    if constexpr ((L << LI) <= kMaxPoints) {                                                        \
-      if (a.front) hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI, true>), grid, block, lds, s, a); \
-      else hipLaunchKernelGGL((fc_tx_pruned_kernel<IO, L, LI, false>), grid, block, lds, s, a);     \
-      return hipGetLastError();                                                                     \
-    }                                                                                               \
+    if constexpr ((L << LI) <= kMaxPoints) return launch_pruned_li<IO, L, LI>(a, lds, s, grid);      \
     break;
     FC_LI(1) FC_LI(2) FC_LI(3) FC_LI(4) FC_LI(5) FC_LI(6) FC_LI(7) FC_LI(8)
 #undef FC_LI
@@ -1582,15 +1607,19 @@ hipError_t launch_size(int cls, const LaunchArgs& a, int aux, size_t lds, hipStr
     if constexpr (is_pow2c(SZ)) return launch_pruned<IO, SZ>(a, aux, lds, s, grid);
     else return hipErrorInvalidValue;        // mixed-radix groups use the full-transform kernel
   }
+  // the RX family under transform plan a.tplan where the size has a second plan
+  constexpr bool alt = rx_has_alt(SZ);
   if (cls == 1) {
     if (a.front) hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ, true>), grid, block, lds, s, a, aux);
     else hipLaunchKernelGGL((fc_tx_full_kernel<IO, SZ, false>), grid, block, lds, s, a, aux);
   } else if (cls == 3) {
     hipLaunchKernelGGL((fc_wgrad_kernel<IO, SZ>), grid, block, lds, s, a, aux);
   } else if (cls == 4) {
-    hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ>), grid, block, lds, s, a, aux);
+    if (alt && a.tplan) hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ, alt ? 1 : 0>), grid, block, lds, s, a, aux);
+    else hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ, 0>), grid, block, lds, s, a, aux);
   } else {
-    hipLaunchKernelGGL((fc_rx_kernel<IO, SZ>), grid, block, lds, s, a, aux);
+    if (alt && a.tplan) hipLaunchKernelGGL((fc_rx_kernel<IO, SZ, alt ? 1 : 0>), grid, block, lds, s, a, aux);
+    else hipLaunchKernelGGL((fc_rx_kernel<IO, SZ, 0>), grid, block, lds, s, a, aux);
   }
   return hipGetLastError();
 }
@@ -1621,49 +1650,48 @@ hipError_t launch_zero_io(void* out, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class K>
+void grant_lds(K* kernel, size_t bytes, hipError_t& e) {
+  const hipError_t r = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (r != hipSuccess) e = r;
+}
+
 template <int IO, int L>
-hipError_t lds_limit_pruned(size_t bytes) {
-  hipError_t e = hipSuccess;
+void lds_limit_pruned(size_t bytes, hipError_t& e) {
 #define FC_LI(LI)                                                                                   \
   if constexpr ((L << LI) <= kMaxPoints) {                                                          \
-    hipError_t r = hipFuncSetAttribute((const void*)fc_tx_pruned_kernel<IO, L, LI, false>,          \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);     \
-    hipError_t rf = hipFuncSetAttribute((const void*)fc_tx_pruned_kernel<IO, L, LI, true>,          \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
-    if (r != hipSuccess) e = r;                                                                     \
-    if (rf != hipSuccess) e = rf;                                                                   \
+    grant_lds(fc_tx_pruned_kernel<IO, L, LI, false, 0>, bytes, e);                                  \
+    grant_lds(fc_tx_pruned_kernel<IO, L, LI, true, 0>, bytes, e);                                   \
+    if constexpr (pruned_has_alt(L)) {                                                              \
+      grant_lds(fc_tx_pruned_kernel<IO, L, LI, false, 1>, bytes, e);                                \
+      grant_lds(fc_tx_pruned_kernel<IO, L, LI, true, 1>, bytes, e);                                 \
+    }                                                                                               \
   }
   FC_LI(1) FC_LI(2) FC_LI(3) FC_LI(4) FC_LI(5) FC_LI(6) FC_LI(7) FC_LI(8)
 #undef FC_LI
-  return e;
+}
+
+template <int IO, int SZ>
+void lds_limits_size(size_t bytes, hipError_t& e) {
+  if constexpr (is_pow2c(SZ)) lds_limit_pruned<IO, SZ>(bytes, e);
+  grant_lds(fc_tx_full_kernel<IO, SZ, false>, bytes, e);
+  grant_lds(fc_tx_full_kernel<IO, SZ, true>, bytes, e);
+  grant_lds(fc_rx_kernel<IO, SZ, 0>, bytes, e);
+  grant_lds(fc_rxd_kernel<IO, SZ, 0>, bytes, e);
+  if constexpr (rx_has_alt(SZ)) {
+    grant_lds(fc_rx_kernel<IO, SZ, 1>, bytes, e);
+    grant_lds(fc_rxd_kernel<IO, SZ, 1>, bytes, e);
+  }
+  grant_lds(fc_wgrad_kernel<IO, SZ>, bytes, e);
 }
 
 template <int IO>
 hipError_t lds_limits_io(size_t bytes) {
   hipError_t e = hipSuccess;
-#define FC_SZ(SZ)                                                                                   \
-  {                                                                                                 \
-    hipError_t r1 = is_pow2c(SZ) ? lds_limit_pruned<IO, is_pow2c(SZ) ? SZ : 16>(bytes) : hipSuccess;   \
-    hipError_t r2 = hipFuncSetAttribute((const void*)fc_tx_full_kernel<IO, SZ, false>,              \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
-    hipError_t r2f = hipFuncSetAttribute((const void*)fc_tx_full_kernel<IO, SZ, true>,              \
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);   \
-    if (r2f != hipSuccess) e = r2f;                                                                 \
-    hipError_t r3 = hipFuncSetAttribute((const void*)fc_rx_kernel<IO, SZ>,                          \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
-    hipError_t r4 = hipFuncSetAttribute((const void*)fc_wgrad_kernel<IO, SZ>,                       \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
-    hipError_t r5 = hipFuncSetAttribute((const void*)fc_rxd_kernel<IO, SZ>,                         \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);    \
-    if (r5 != hipSuccess) e = r5;                                                                   \
-    if (r1 != hipSuccess) e = r1;                                                                   \
-    if (r2 != hipSuccess) e = r2;                                                                   \
-    if (r3 != hipSuccess) e = r3;                                                                   \
-    if (r4 != hipSuccess) e = r4;                                                                   \
-  }
-  FC_SZ(16) FC_SZ(32) FC_SZ(64) FC_SZ(128) FC_SZ(256) FC_SZ(512) FC_SZ(1024) FC_SZ(2048) FC_SZ(4096)
-  FC_SZ(768) FC_SZ(1536) FC_SZ(3072)
-#undef FC_SZ
+  lds_limits_size<IO, 16>(bytes, e); lds_limits_size<IO, 32>(bytes, e); lds_limits_size<IO, 64>(bytes, e);
+  lds_limits_size<IO, 128>(bytes, e); lds_limits_size<IO, 256>(bytes, e); lds_limits_size<IO, 512>(bytes, e);
+  lds_limits_size<IO, 1024>(bytes, e); lds_limits_size<IO, 2048>(bytes, e); lds_limits_size<IO, 4096>(bytes, e);
+  lds_limits_size<IO, 768>(bytes, e); lds_limits_size<IO, 1536>(bytes, e); lds_limits_size<IO, 3072>(bytes, e);
   return e;
 }
 

@@ -40,23 +40,32 @@ constexpr bool divides_pow2(int L, int N) { return L <= N && N % L == 0 && is_po
 // block; four or three blocks where that lets three workgroups share a CU
 // (one idle wave in the short-FFT phase costs less than a third workgroup
 // gains), else the most of {4, 2, 1} that lets two share it.
+//
+// Transform plans (tuning, chosen by the autotuner): plan 0 takes the rule
+// above; plan 1 the other placement of the short FFTs where both exist
+// (L <= 1024). For the RX family plan 1 takes the long FFT with the next
+// lower radix cap (radix 8 passes at N = 4096, radix 4 at N = 2048).
 constexpr int pruned_lds_entries(int L, int N, int nb) { return lds_elems(N) + N / 2 + nb * lds_elems(L); }
 constexpr bool pruned_wave_short(int L, int N) { return L < 256 || (L <= 1024 && N < 2048); }
-constexpr int pruned_group_blocks(int L, int N) {
-  return !pruned_wave_short(L, N) ? 1
+constexpr bool pruned_ws(int L, int N, int tp) {
+  return tp == 0 ? pruned_wave_short(L, N) : (L <= 1024 && !pruned_wave_short(L, N));
+}
+constexpr bool pruned_has_alt(int L) { return L <= 1024; }
+constexpr int pruned_group_blocks(int L, int N, int tp = 0) {
+  return !pruned_ws(L, N, tp) ? 1
          : pruned_lds_entries(L, N, 4) * 8 <= 163840 / 3 ? 4
          : pruned_lds_entries(L, N, 3) * 8 <= 163840 / 3 ? 3
          : pruned_lds_entries(L, N, 4) * 8 <= 80 * 1024 ? 4
          : pruned_lds_entries(L, N, 2) * 8 <= 80 * 1024 ? 2 : 1;
 }
-constexpr int pruned_lds_bytes(int L, int N) {
-  return pruned_lds_entries(L, N, pruned_wave_short(L, N) ? pruned_group_blocks(L, N) : 0) * 8;
+constexpr int pruned_lds_bytes(int L, int N, int tp = 0) {
+  return pruned_lds_entries(L, N, pruned_ws(L, N, tp) ? pruned_group_blocks(L, N, tp) : 0) * 8;
 }
 // Workgroups per CU that the LDS allows (160 KiB per CU), at most three: the
 // register budget follows, so that registers do not lower the occupancy the
 // LDS allows, without forcing spills where LDS would allow four.
-constexpr int pruned_waves_per_simd(int L, int N) {
-  return 163840 / pruned_lds_bytes(L, N) >= 3 ? 3 : 163840 / pruned_lds_bytes(L, N);
+constexpr int pruned_waves_per_simd(int L, int N, int tp = 0) {
+  return 163840 / pruned_lds_bytes(L, N, tp) >= 3 ? 3 : 163840 / pruned_lds_bytes(L, N, tp);
 }
 
 // Weight gradient of a one-subband group with L <= 1024, blocks in groups:
@@ -134,6 +143,9 @@ constexpr int twb_off(int P, int s, int RM = 16) {
 constexpr int twb_total() { return twb_plan_total(16) + twb_plan_total(8) + twb_plan_total(4); }
 // largest radix for interleaved transforms of N points in all on 256 threads
 constexpr int radix_cap(int N) { return N >= 4096 ? 16 : (N >= 2048 ? 8 : 4); }
+// long FFT of the RX family under transform plan tp
+constexpr int rx_long_cap(int N, int tp) { return tp && radix_cap(N) > 4 ? radix_cap(N) / 2 : radix_cap(N); }
+constexpr bool rx_has_alt(int N) { return is_pow2c(N) && rx_long_cap(N, 1) != rx_long_cap(N, 0); }
 // the same for one P-point transform on one wave (64 threads): radix 16 for
 // 1024 points, 8 for 512, 4 below, so that from 256 points up every lane
 // holds a butterfly in every pass (radix-16 passes left 48 of the 64 lanes
@@ -228,6 +240,7 @@ struct LaunchArgs {
   const void* in2;           // weight gradient: the forward low-rate input
   int32_t front;             // TX: 1 = input is the QAM grid (OFDM modulation in the kernel)
   float* part;               // weight gradient: per-task partial sums (scratch)
+  int32_t tplan;             // transform plan (0 or 1, see pruned_ws / rx_long_cap)
 };
 
 }  // namespace fcx

@@ -17,6 +17,7 @@
 #include <numeric>
 #include <string>
 #include <tuple>
+#include <unordered_map>
 #include <vector>
 
 #include "fc.h"
@@ -127,6 +128,7 @@ struct fc_plan {
   Cf* d_twp = nullptr;           // per-pass twiddle bases
   Op op[kOps];                        // FC_OP_TX .. FC_OP_TXG, then the weight gradient's schedule
   int run_len[5] = {0, 0, 0, 0, 0};   // blocks per task per op (0: planner heuristic)
+  int tplan[5] = {0, 0, 0, 0, 0};     // transform plan per op (0 or 1: pruned_ws, rx_long_cap)
   int conc[5] = {kMaxConc, kMaxConc, kMaxConc, kMaxConc, kMaxConc};   // per op: launches of one independent set in flight
   hipStream_t side[kMaxConc - 1] = {};
   hipEvent_t ev_fork = nullptr;
@@ -306,6 +308,7 @@ void build_op(fc_plan* P, int op_index) {
     ogroups.push_back(cur);
   }
   // subband table in group order
+  std::unordered_map<uint64_t, int> map_by_hash;     // RX scatter maps by content: group holding it
   for (size_t g = 0; g < ogroups.size(); ++g) {
     const OpGroup& OG = ogroups[g];
     const Group& G = P->groups[OG.pg];
@@ -350,6 +353,22 @@ void build_op(fc_plan* P, int op_index) {
           cnt[q]++;
         }
         if (d.L > 1024) gr.n_long_sb++;
+      }
+      // groups with the same subband layout (every frame of a batch of
+      // frames) share one copy of the map, so that the copy stays in cache
+      // instead of one copy per group streaming through it
+      {
+        uint64_t hsh = 1469598103934665603ull ^ (uint64_t)gr.N;      // FNV-1a over the entries
+        for (int q = 0; q < gr.N; ++q) hsh = (hsh ^ op.rxmap[gr.map_off + q]) * 1099511628211ull;
+        auto it = map_by_hash.find(hsh);
+        if (it != map_by_hash.end() && op.grp[it->second].N == gr.N &&
+            std::equal(op.rxmap.begin() + op.grp[it->second].map_off,
+                       op.rxmap.begin() + op.grp[it->second].map_off + gr.N, op.rxmap.begin() + gr.map_off)) {
+          op.rxmap.resize(gr.map_off);
+          gr.map_off = op.grp[it->second].map_off;
+        } else if (it == map_by_hash.end()) {
+          map_by_hash[hsh] = (int)g;
+        }
       }
       // spread the one-wave short IFFTs (L <= 1024) over the four waves,
       // largest first onto the least loaded wave
@@ -524,7 +543,7 @@ void build_op(fc_plan* P, int op_index) {
         if (gd.prune) {
           ct.aux = ilog2(s0.I);
           // long IFFT buffer, OLA carry, and (L <= 1024) the short-FFT / band regions
-          ct.lds = std::max(ct.lds, (size_t)pruned_lds_bytes(s0.L, N));
+          ct.lds = std::max(ct.lds, (size_t)pruned_lds_bytes(s0.L, N, P->tplan[kind]));
         } else {
           ct.aux = std::max(ct.aux, lmax);
           ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + lds_elems(ct.aux) + N / 2) * 8);
@@ -642,6 +661,8 @@ hipError_t launch_phase(fc_plan* P, const Op& op, const Op::Phase& ph, const voi
   a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
   a.in = in; a.out = out;
   a.front = &op == &P->op[FC_OP_TXG] ? 1 : 0;
+  const int k = (int)(&op - P->op);
+  a.tplan = k < 5 ? P->tplan[k] : 0;
   return launch_kernel(ph.cls, ph.size, a, ph.aux, ph.lds, st);
 }
 
@@ -1065,6 +1086,40 @@ fc_status fc_plan_get_tuning(const fc_plan* P, int32_t op, int32_t* run_len, int
   return FC_OK;
 }
 
+fc_status fc_plan_set_transform_plan(fc_plan* P, int32_t op, int32_t tplan) {
+  if (!P || op < 0 || op > 4 || tplan < 0 || tplan > 1) return FC_E_ARG;
+  if (!P->op[op].valid) return FC_E_STATE;
+  if (P->device >= 0) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
+    const bool ok = hipDeviceSynchronize() == hipSuccess;
+    P->tplan[op] = tplan;
+    const fc_status st = ok ? rebuild_op(P, op) : FC_E_DEVICE;
+    (void)hipSetDevice(cur);
+    return st;
+  }
+  P->tplan[op] = tplan;
+  return rebuild_op(P, op);
+}
+
+fc_status fc_plan_get_transform_plan(const fc_plan* P, int32_t op, int32_t* tplan) {
+  if (!P || op < 0 || op > 4 || !tplan) return FC_E_ARG;
+  *tplan = P->tplan[op];
+  return FC_OK;
+}
+
+// Whether transform plan 1 differs from plan 0 for some launch of op: a
+// pruned TX class with L <= 1024, or an RX-family launch with a long FFT
+// whose radix cap can be lowered.
+static bool has_second_plan(const fc_plan* P, int op) {
+  for (const auto& ph : P->op[op].phases) {
+    if (ph.kind == 2) continue;
+    if (ph.cls == 0 && pruned_has_alt(ph.size)) return true;
+    if ((ph.cls == 2 || ph.cls == 4) && rx_has_alt(ph.size)) return true;
+  }
+  return false;
+}
+
 // Time of one call of op under the current tuning: the minimum over six
 // calls after a warm-up. On a capturable stream the call is recorded once as
 // a HIP graph and the graph is replayed, so host launch gaps between the op's
@@ -1111,17 +1166,22 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
   fc_status result = FC_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) result = FC_E_DEVICE;
   float best = 1e30f;
-  int b_len = P->run_len[op], b_conc = P->conc[op];
-  for (int conc : {1, kMaxConc}) {
-    for (int len : lens) {
-      if (result != FC_OK) break;
-      if ((result = fc_plan_set_tuning(P, op, len, conc)) != FC_OK) break;
-      if (conc > 1 && (result = measure_costs(P, op, in, out, st, e0, e1)) != FC_OK) break;
-      float t_min = 1e30f;
-      result = time_op(P, op, in, out, st, e0, e1, &t_min);
-      if (result == FC_OK && t_min < best) { best = t_min; b_len = len; b_conc = conc; }
+  int b_len = P->run_len[op], b_conc = P->conc[op], b_tp = P->tplan[op];
+  const int n_tp = has_second_plan(P, op) ? 2 : 1;
+  for (int tp = 0; tp < n_tp && result == FC_OK; ++tp) {
+    P->tplan[op] = tp;                     // applied by the rebuilds of set_tuning below
+    for (int conc : {1, kMaxConc}) {
+      for (int len : lens) {
+        if (result != FC_OK) break;
+        if ((result = fc_plan_set_tuning(P, op, len, conc)) != FC_OK) break;
+        if (conc > 1 && (result = measure_costs(P, op, in, out, st, e0, e1)) != FC_OK) break;
+        float t_min = 1e30f;
+        result = time_op(P, op, in, out, st, e0, e1, &t_min);
+        if (result == FC_OK && t_min < best) { best = t_min; b_len = len; b_conc = conc; b_tp = tp; }
+      }
     }
   }
+  P->tplan[op] = b_tp;
   if (result == FC_OK) result = fc_plan_set_tuning(P, op, b_len, b_conc);
   if (result == FC_OK && b_conc > 1) result = measure_costs(P, op, in, out, st, e0, e1);
   if (e0) (void)hipEventDestroy(e0);

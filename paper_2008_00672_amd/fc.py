@@ -52,6 +52,8 @@ EXPORTS = {
     "fc_tx_weight_grad_noalloc": (_I32, [_P, _P, _P, _P, _P]),
     "fc_plan_set_tuning": (_I32, [_P, _I32, _I32, _I32]),
     "fc_plan_get_tuning": (_I32, [_P, _I32, _I32P, _I32P]),
+    "fc_plan_set_transform_plan": (_I32, [_P, _I32, _I32]),
+    "fc_plan_get_transform_plan": (_I32, [_P, _I32, _I32P]),
     "fc_plan_autotune": (_I32, [_P, _I32, _P, _P, _P, _I32P, _I32P, ctypes.POINTER(ctypes.c_float)]),
     "fc_graph_begin": (_I32, [_P]),
     "fc_graph_end": (_I32, [_P, ctypes.POINTER(_P)]),
@@ -324,9 +326,18 @@ class Plan:
         _check(lib().fc_plan_get_tuning(self._h, op, ctypes.byref(r), ctypes.byref(c)), "fc_plan_get_tuning")
         return dict(run_len=r.value, conc=c.value)
 
+    def set_transform_plan(self, op, tplan):
+        _check(lib().fc_plan_set_transform_plan(self._h, op, tplan), "fc_plan_set_transform_plan")
+
+    def get_transform_plan(self, op):
+        t = ctypes.c_int32()
+        _check(lib().fc_plan_get_transform_plan(self._h, op, ctypes.byref(t)), "fc_plan_get_transform_plan")
+        return t.value
+
     def autotune(self, op, inp, out, stream=None):
-        """Time the op's work splits on these buffers (out is overwritten) and
-        keep the fastest; returns the choice and its time per call."""
+        """Time the op's work splits and transform plans on these buffers (out
+        is overwritten) and keep the fastest; returns the choice and its time
+        per call."""
         lo, hi = self.layout(op)
         n_in, n_out = (int(lo[-1]), int(hi[-1])) if op in (OP_TX, OP_TXG) else (int(hi[-1]), int(lo[-1]))
         self._check_buf(inp, n_in, "input")
@@ -334,7 +345,7 @@ class Plan:
         r, c, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
         _check(lib().fc_plan_autotune(self._h, op, _ptr(inp), _ptr(out), _stream_handle(stream), ctypes.byref(r),
                                       ctypes.byref(c), ctypes.byref(ms)), "fc_plan_autotune")
-        return dict(run_len=r.value, conc=c.value, ms=ms.value)
+        return dict(run_len=r.value, conc=c.value, plan=self.get_transform_plan(op), ms=ms.value)
 
 
 class Graph:

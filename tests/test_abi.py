@@ -211,6 +211,25 @@ def test_tuning_host_plan():
             p.set_tuning(fc.OP_TX, **dict(dict(run_len=0, conc=4), **bad))
 
 
+def test_transform_plan_host_plan():
+    """Transform plans 0/1 per op: set, read back, the blocks unchanged;
+    out-of-range values rejected."""
+    fc = _lib()
+    sbs, _ = W.batched_carriers(n_carriers=8)
+    p = _plan(sbs, io="f16")
+    base = p.stats(fc.OP_TX)
+    for op in (fc.OP_TX, fc.OP_RX, fc.OP_ADJ, fc.OP_RXD, fc.OP_TXG):
+        assert p.get_transform_plan(op) == 0
+        p.set_transform_plan(op, 1)
+        assert p.get_transform_plan(op) == 1
+    assert p.stats(fc.OP_TX)["blocks"] == base["blocks"]
+    for bad in (-1, 2):
+        with pytest.raises(fc.FcError, match="invalid argument"):
+            p.set_transform_plan(fc.OP_TX, bad)
+    with pytest.raises(fc.FcError, match="invalid argument"):
+        p.set_transform_plan(7, 0)
+
+
 def test_autotune_host_plan_rejected():
     """The autotuner needs a device plan: a host-only plan gets FC_E_STATE and
     missing buffers or an unknown op FC_E_ARG, before any device call; the

@@ -92,6 +92,76 @@ def test_weight_grad_is_deterministic(shape):
             assert same
 
 
+@pytest.mark.parametrize("op", ["tx", "tx_grid", "rx", "rx_demod", "adjoint"])
+def test_transform_plan_1_parity(op):
+    """Transform plan 1 (the other short-FFT placement of the pruned TX, the
+    lower-radix long FFT of the RX family) against the oracle: the TX on 12
+    batched carriers (FP16), the RX family on the 100 MHz filter bank (14
+    symbols, FP32)."""
+    import torch
+    from fc_cases import assert_gate, oracle_adj, oracle_rx, oracle_rxd, oracle_tx, oracle_tx_grid
+    from paper_2008_00672_amd import OP_ADJ, OP_RX, OP_RXD, OP_TX, OP_TXG
+    print("case: transform plan 1, %s" % op, flush=True)
+    if op in ("tx", "tx_grid"):
+        sbs, meta = W.batched_carriers(n_carriers=12)
+        xs, Ds, grids = make_inputs(sbs, meta["qam"], meta["seed"], "rc")
+        p = _plan(sbs, "f16", Ds)
+        code = OP_TX if op == "tx" else OP_TXG
+        p.set_transform_plan(code, 1)
+        _, hi = p.layout(code)
+        if op == "tx":
+            y, ref = p.tx(to_device(_cat(xs), "f16")), oracle_tx(sbs, xs, Ds)
+        else:
+            y = p.tx_grid(to_device(np.concatenate([g.ravel() for g in grids]), "f16"))
+            ref = oracle_tx_grid(sbs, grids, Ds)
+        torch.cuda.synchronize()
+        f = y.to(torch.float32).cpu().numpy()
+        assert_gate(_split(f[:, 0] + 1j * f[:, 1], hi), ref, "f16", op)
+        return
+    fb, meta = W.rx_filterbank(14)
+    sbs = [dict(s, mode="sync_ola") for s in fb]
+    _, Ds, _ = make_inputs(sbs, 4, 5, "rc")
+    p = _plan(sbs, "c64", Ds)
+    code = {"rx": OP_RX, "rx_demod": OP_RXD, "adjoint": OP_ADJ}[op]
+    p.set_transform_plan(code, 1)
+    _, lens, _ = stream_offsets(sbs)
+    rng = np.random.default_rng(6)
+    st = rng.standard_normal(lens[0]) + 1j * rng.standard_normal(lens[0])
+    lo, _ = p.layout(code)
+    call = {"rx": p.rx, "rx_demod": p.rx_demod, "adjoint": p.adjoint}[op]
+    z = call(to_device(st, "c64"))
+    torch.cuda.synchronize()
+    ref = {"rx": oracle_rx, "rx_demod": oracle_rxd, "adjoint": oracle_adj}[op](sbs, [st], Ds)
+    assert_gate(_split(z.cpu().numpy().astype(np.complex128), lo), ref, "c64", op)
+
+
+def test_autotune_chooses_transform_plan():
+    """The autotuner sweeps both transform plans where they differ and keeps a
+    choice whose output still meets the gate."""
+    import torch
+    from fc_cases import assert_gate
+    from paper_2008_00672_amd import OP_RX
+    fb, meta = W.rx_filterbank(28)
+    sbs = [dict(s, mode="sync_ola", stream=f) for f in range(8) for s in fb]
+    _, Ds, _ = make_inputs(sbs, 4, 5, "rc")
+    p = _plan(sbs, "c64", Ds)
+    _, lens, _ = stream_offsets(sbs)
+    rng = np.random.default_rng(7)
+    st = to_device(rng.standard_normal(sum(lens)) + 1j * rng.standard_normal(sum(lens)), "c64")
+    z = p.empty(int(p.layout(OP_RX)[0][-1]))
+    best = p.autotune(OP_RX, st, z, stream=torch.cuda.Stream())
+    print("autotune RX with transform plans:", best, flush=True)
+    assert best["plan"] in (0, 1) and p.get_transform_plan(OP_RX) == best["plan"]
+    ref = p.rx(st).clone()
+    p.set_transform_plan(OP_RX, 1 - best["plan"])
+    other = p.rx(st)
+    torch.cuda.synchronize()
+    lo, _ = p.layout(OP_RX)
+    a = _split(ref.cpu().numpy().astype(np.complex128), lo)
+    b = _split(other.cpu().numpy().astype(np.complex128), lo)
+    assert_gate(a, b, "c64", "plan 0 against plan 1")
+
+
 def test_graph_replay_matches_eager():
     """TX and RX of two plans captured in one graph; three replays, each
     after eager work that clobbers the outputs, each equal to the eager call."""
@@ -166,8 +236,14 @@ def test_autotune_keeps_results(side_stream):
     torch.cuda.synchronize()
     best = p.autotune(OP_TX, x, out, stream=s)
     print("autotune TX (%s):" % ("side stream" if side_stream else "null stream"), best, flush=True)
-    assert best["run_len"] in (0, 8, 16, 32, 64) and best["conc"] in (1, 4) and best["ms"] > 0
+    assert best["run_len"] in (0, 8, 16, 32, 64) and best["conc"] in (1, 4) and best["plan"] in (0, 1)
+    assert best["ms"] > 0
     assert p.get_tuning(OP_TX) == dict(run_len=best["run_len"], conc=best["conc"])
     y = p.tx(x, stream=s)
     torch.cuda.synchronize()
-    assert torch.equal(y, ref)
+    if best["plan"] == 0:
+        assert torch.equal(y, ref)           # same transform plan: the same bits
+    else:                                    # the other plan rounds differently
+        from fc_cases import assert_gate
+        f, g = y.to(torch.float32).cpu().numpy(), ref.to(torch.float32).cpu().numpy()
+        assert_gate([f[:, 0] + 1j * f[:, 1]], [g[:, 0] + 1j * g[:, 1]], "f16", "plan 1 against plan 0")

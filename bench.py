@@ -246,11 +246,14 @@ def wgrad_cost(sbs):
     return flops
 
 
-def traffic(op, run_len):
+def traffic(op, run_len, plan=0):
     """HBM bytes per call of op at run_len blocks per task from the committed
     rocprofv3 counter summary (profiles/traffic_<op>.json), or None when the
-    kernel sources changed since the counters were taken or no counters were
-    taken at that run length."""
+    kernel sources changed since the counters were taken, no counters were
+    taken at that run length, or the op runs transform plan 1 (the counters
+    are taken with plan 0)."""
+    if plan:
+        return None
     from paper_2008_00672_amd.profsum import kernel_hash
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % op)
     if not os.path.exists(path):
@@ -865,7 +868,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
-    roof["traffic"] = traffic(dk, tune["rx"]["run_len"])
+    roof["traffic"] = traffic(dk, tune["rx"]["run_len"], tune["rx"].get("plan", 0))
     roof["kernel"] = "fc_rx_kernel<bf16, N=4096> (one launch per RX call)"
     roof["algorithmic_bytes"] = int(d_bytes)
     roof["algorithmic_flops"] = int(d_flops)
@@ -879,7 +882,8 @@ def main():
                             "achieved_tflops": round(tx_tf, 2), "flops": "executed (long IFFT pruned to the band)",
                             "achieved_tflops_nominal": round(tx_flops_nominal / tx_ms / 1e9, 2),
                             "hbm_gbs": round(tx_bytes / tx_ms / 1e6, 1), "algorithmic_bytes": int(tx_bytes),
-                            "algorithmic_flops": int(tx_flops), "traffic": traffic("fc_tx", tune["tx"]["run_len"])},
+                            "algorithmic_flops": int(tx_flops),
+                            "traffic": traffic("fc_tx", tune["tx"]["run_len"], tune["tx"].get("plan", 0))},
                            **frac(tx_tf))
 
     # ---------------- launch overhead of unbatched calls ----------------

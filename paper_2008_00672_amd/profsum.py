@@ -81,10 +81,19 @@ def _copy_reading(path, counter):
     return top[len(top) // 2]
 
 
+def _tx_front(k):
+    """The FRONT template argument of a TX kernel name (fc_tx_pruned_kernel<IO,
+    L, log2 I, FRONT, plan> or fc_tx_full_kernel<IO, N, FRONT>), else None."""
+    if not k.startswith("fc_tx_") or "<" not in k:
+        return None
+    args = [a.strip() for a in k[k.index("<") + 1:k.rindex(">")].split(",")]
+    return next((a for a in args if a in ("true", "false")), None)
+
+
 # kernels of one call of each operation
 OPS = {
-    "fc_tx": lambda k: k.startswith("fc_tx_") and k.endswith("false>"),       # TX from the low-rate signal
-    "fc_tx_grid": lambda k: k.startswith("fc_tx_") and k.endswith("true>"),   # TX from the QAM grid
+    "fc_tx": lambda k: _tx_front(k) == "false",       # TX from the low-rate signal
+    "fc_tx_grid": lambda k: _tx_front(k) == "true",   # TX from the QAM grid
     "fc_rx": lambda k: k.startswith("fc_rx_kernel"),
     "fc_rxd": lambda k: k.startswith("fc_rxd_kernel"),
 }

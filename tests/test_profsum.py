@@ -20,7 +20,7 @@ def _csv(path, rows):
 
 def _files(tmp_path, fetch_kib, write_kib):
     rx = "void fcx::fc_rx_kernel<2, 4096>(fcx::LaunchArgs, int)"
-    tx = "void fcx::fc_tx_pruned_kernel<1, 2048, 1, false>(fcx::LaunchArgs, int)"
+    tx = "void fcx::fc_tx_pruned_kernel<1, 2048, 1, false, 0>(fcx::LaunchArgs, int)"
     f = _csv(tmp_path / "f.csv", [[rx, "FETCH_SIZE", fetch_kib]] * 3 + [[tx, "FETCH_SIZE", 999.0]])
     w = _csv(tmp_path / "w.csv", [[rx, "WRITE_SIZE", write_kib]] * 3 + [[tx, "WRITE_SIZE", 999.0]])
     # three 256 MiB copies (the median is taken) plus a small unrelated copy;

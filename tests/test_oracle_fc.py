@@ -74,7 +74,7 @@ def test_lin_i1_is_np_convolve():
     assert rel(y[ov.L_O - 3:ov.L_O - 3 + len(conv)], conv) < 1e-12
 
 
-def _cfg1_signal():
+def _plain_slot_signal():
     sbs, meta = fcsynth.workloads.plain_tx_slot()
     s = sbs[0]
     L, N, K = s["n_short"], s["n_long"], s["n_active"]
@@ -87,7 +87,7 @@ def _cfg1_signal():
 def test_fc_approximates_linear_convolution():
     """O-FC against O-LIN: FC is an approximation of linear convolution; with
     50 % overlap and an 8-bin RC transition it is close (bounded, not exact)."""
-    s, x, D = _cfg1_signal()
+    s, x, D = _plain_slot_signal()
     L, N = s["n_short"], s["n_long"]
     e_ols = metrics.err_db(fc.tx_cont(x, L, N, 0, D, ola=False), lin.tx_cont_lin(x, L, N, 0, D))
     e_ola = metrics.err_db(fc.tx_cont(x, L, N, 0, D, ola=True), lin.tx_cont_lin(x, L, N, 0, D))

@@ -1,10 +1,11 @@
-"""Seeded random plans against the FP64 oracle: modes, sizes, centres,
-overlaps, smooth edges, CP schedules, and subbands sharing a stream.
+"""Seeded random plans against the FP64 oracle: modes, sizes (powers of two,
+and mixed radix), centres, overlaps, smooth edges, CP schedules, and
+subbands sharing a stream.
 
 Each configuration is drawn from a fixed seed and kept only if a host-only
 plan accepts it (so every drawn case is one the library declares valid); the
-TX, the RX, and where the mode has them the adjoint and the demodulating RX
-are compared with the oracle under the FP32 gate."""
+TX, the RX, and where the mode has them the adjoint, the weight gradient and
+the demodulating RX are compared with the oracle under the FP32 gate."""
 import numpy as np
 import pytest
 
@@ -17,15 +18,16 @@ pytestmark = pytest.mark.gpu
 MODES = ["cont_ola", "cont_ols", "sync_ola", "sync_ols"]
 
 
-def draw(seed):
-    """One valid plan (list of subbands) from the seed."""
+def draw(seed, mixed_radix=False):
+    """One valid plan (list of subbands) from the seed: power-of-two sizes, or
+    (mixed_radix) N in {768, 1536, 3072} with L in {768, 1536}."""
     from paper_2008_00672_amd import FcError, Plan
     rng = np.random.default_rng(seed)
     while True:
         mode = MODES[int(rng.integers(0, 4))]
         sync = mode.startswith("sync")
         n_sb = int(rng.integers(1, 4))
-        N = int(2 ** rng.integers(6, 11))                  # 64 .. 1024
+        N = int(768 << rng.integers(0, 3)) if mixed_radix else int(2 ** rng.integers(6, 11))   # 64 .. 1024
         n_sym = int(rng.integers(1, 5))
         lam = (1, 2) if sync or rng.random() < 0.6 else (1, 4)
         # one CP schedule per plan (subbands sharing a stream share it)
@@ -39,7 +41,10 @@ def draw(seed):
             taper = 2 * int(rng.integers(1, max(2, (N // 4 - max(ncp)) // 2 + 1)))
         sbs = []
         for m in range(n_sb):
-            L = int(min(N, 2 ** rng.integers(4, 9)))       # 16 .. 256
+            if mixed_radix:
+                L = int(min(N, 768 << rng.integers(0, 2)))  # 768, 1536
+            else:
+                L = int(min(N, 2 ** rng.integers(4, 9)))   # 16 .. 256
             n_tb = int(rng.integers(0, 5))
             K = 2 * int(rng.integers(0, (L - 2 * n_tb) // 2 + 1))
             cmax = N // 2 - L // 2
@@ -60,11 +65,44 @@ def draw(seed):
 
 
 SEEDS = list(range(100, 124))
+MIXED_SEEDS = list(range(200, 208))
 
 
-@pytest.mark.parametrize("seed", SEEDS)
+def _check_wgrad(sbs, seed):
+    """Weight gradient on six random bins per subband against the oracle.
+    The bins are drawn from the input's active band and transition bins
+    (outside it the input has almost no energy and the gradient almost
+    vanishes, so its relative error measures FP32 noise on near-zero values);
+    subbands without active subcarriers are skipped."""
+    import torch
+    from fc_cases import make_inputs, oracle_wgrad, stream_offsets, to_device
+    from oracle import metrics
+    from test_gpu_parity import _cat, _plan, _split
+    xs, Ds, _ = make_inputs(sbs, 16, seed, "random")
+    p = _plan(sbs, "c64", Ds)
+    _, lens, _ = stream_offsets(sbs)
+    rng = np.random.default_rng(seed + 1)
+    gs = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in lens]
+    gw = p.weight_grad(to_device(_cat(xs), "c64"), to_device(_cat(gs), "c64"))
+    torch.cuda.synchronize()
+    offs = np.concatenate([[0], np.cumsum([s["n_short"] for s in sbs])])
+    got = _split(gw.cpu().numpy().astype(np.float64), offs)
+    bins = []
+    for s in sbs:
+        L, K, ntb = s["n_short"], s["n_active"], s["n_tb"]
+        band = np.arange(L // 2 - K // 2 - ntb, L // 2 + K // 2 + ntb)
+        bins.append(sorted(rng.choice(band, size=min(6, len(band)), replace=False).tolist()) if K else [])
+    for k, (g, r, b) in enumerate(zip(got, oracle_wgrad(sbs, xs, gs, bins), bins)):
+        if not b:
+            continue
+        e = metrics.err_db(g[b], r[b])
+        print("random weight gradient %d, subband %d: err %.1f dB" % (seed, k, e), flush=True)
+        assert e <= -90.0
+
+
+@pytest.mark.parametrize("seed", SEEDS + MIXED_SEEDS)
 def test_random_plan(seed):
-    sbs = draw(seed)
+    sbs = draw(seed, mixed_radix=seed in MIXED_SEEDS)
     desc = ", ".join("%s L%d N%d c%d K%d tb%d B%d%s" % (s["mode"], s["n_short"], s["n_long"], s["center_bin"],
                                                         s["n_active"], s["n_tb"], s["n_symbols"],
                                                         " taper%d" % s["taper"] if s["taper"] else "")
@@ -77,6 +115,7 @@ def test_random_plan(seed):
     if all(s["mode"] != "sync_ols" for s in sbs):
         got, ref = run_rx(sbs, "c64", seed=seed, weights="random", adjoint=True)
         assert_gate(got, ref, "c64", "random adjoint %d" % seed)
+        _check_wgrad(sbs, seed)
     if all(s["mode"].startswith("sync") for s in sbs):
         got, ref = run_rx(sbs, "c64", seed=seed, weights="random", demod=True)
         assert_gate(got, ref, "c64", "random demod RX %d" % seed)

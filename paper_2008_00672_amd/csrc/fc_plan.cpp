@@ -371,16 +371,31 @@ void build_op(fc_plan* P, int op_index) {
         }
       }
       // spread the one-wave short IFFTs (L <= 1024) over the four waves,
-      // largest first onto the least loaded wave
+      // costliest first onto the least loaded wave. A one-wave transform
+      // costs per pass its values per lane plus a fixed overhead (the pass's
+      // LDS round trip and wave barrier, about four values' worth): with
+      // L log L as the cost the 8-subband filter bank put 512 + 512 + 256
+      // points (ten passes) on one wave, and the RX took 1.156 ms against
+      // 1.125 ms with this cost
+      auto cost = [&](int i) {
+        const int Lq = op.sb[i].L;
+        if (is_tri(Lq)) {          // three radix-4 sub-transforms of L/3 points, then the combination
+          const int P2 = Lq / 3, vsub = ((P2 / 4) + 63) / 64 * 4;
+          return (double)3 * npass(P2, 4) * (vsub + 4) + 3 * ((P2 + 63) / 64) + 4;
+        }
+        const int rm = wave_radix_cap(Lq);
+        const int vpl = ((Lq / radix_of(Lq, 0, rm)) + 63) / 64 * radix_of(Lq, 0, rm);
+        return (double)npass(Lq, rm) * (vpl + 4);
+      };
       std::vector<int> idx;
       for (int i = 0; i < gr.n_sb; ++i)
         if (op.sb[gr.sb_first + i].L <= 1024) idx.push_back(gr.sb_first + i);
-      std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return op.sb[x].L > op.sb[y].L; });
+      std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost(x) > cost(y); });
       double load[4] = {0, 0, 0, 0};
       for (int i : idx) {
         int w = (int)(std::min_element(load, load + 4) - load);
         op.sb[i].wave = w;
-        load[w] += (double)op.sb[i].L * (op.sb[i].logL + 1);
+        load[w] += cost(i);
       }
       // weight-gradient LDS: spectrum / regions, short-FFT scratch (one per
       // wave, or one workgroup buffer for L > 1024), float accumulators

@@ -144,7 +144,11 @@ typedef struct fc_plan fc_plan;
  * equal numerology, symbol count and CP schedule among subbands sharing a
  * stream and n_long in one processing group). Initialises every subband's
  * weights to a raised-cosine transition of n_tb bins. *plan receives the plan
- * (or NULL on failure). Device memory for the plan's tables is allocated here.
+ * (or NULL on failure). Device memory for the plan's tables is allocated here,
+ * and, when every subband is synchronised, the scratch of fc_rx_demodulate:
+ * 8 bytes per subband bin per workgroup task (sum_m n_short_m x 8 bytes for
+ * each task, a task holding run_len / 2 symbols of one processing group),
+ * reallocated when fc_plan_set_tuning changes FC_OP_RXD.
  */
 fc_status fc_plan_create(const fc_subband* sb, int32_t n_sb, int32_t io_type, int32_t device,
                          fc_plan** plan);
@@ -255,7 +259,10 @@ fc_status fc_tx_modulate(fc_plan* plan, const void* grid_in, void* highrate_out,
  *                    values, symbol by symbol; subcarrier kappa of a symbol at
  *                    index kappa mod n_short), the plan's I/O type.
  * Every subband must be synchronised (FC_SYNC_OLA or FC_SYNC_OLS), else
- * FC_E_STATE. Asynchronous on `stream`; errors as fc_rx_analyze.
+ * FC_E_STATE. Asynchronous on `stream`; errors as fc_rx_analyze. Each task
+ * keeps its symbols' B terms in its own slot of plan-owned device scratch
+ * (allocated with the plan's tables): calls on one plan that overlap in time
+ * on different streams race on it.
  */
 fc_status fc_rx_demodulate(fc_plan* plan, const void* highrate_in, void* subcarriers_out, void* stream);
 

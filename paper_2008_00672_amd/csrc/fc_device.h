@@ -1114,21 +1114,26 @@ __device__ __forceinline__ float2 rot_j(float2 v, int k) {
   return (k & 2) ? make_float2(-r.x, -r.y) : r;
 }
 
-// First pass of the per-symbol IFFT: V[u] = A[u] - B[u], A from the first
-// block (stored), B[u] = g1[u] (-j)^u from the second block's region.
+// First pass of the per-symbol IFFT, in place in the subband's region:
+// V[u] = A[u] - B[u] with A[u] = g0[u] j^u from the first block's spectrum
+// in the region and B[u] = g1[u] (-j)^u from the task's scratch slot, both
+// fetched before the pass.
 template <int NT, int L, int RM> struct LoadV {
-  const float2* A; const float2* R; const float* D; float2 ph;
-  float d[16];
+  const float2* R; const float2* B; const float* D; float2 ph;
+  float d[16]; float2 b[16];
   __device__ __forceinline__ void prefetch(int tid) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      int u, b;
-      if (first_pos<NT, L, 0, RM>(s, tid, u, b)) d[s] = D[wrap(u + (L >> 1), L)];
+      int u, bb;
+      if (first_pos<NT, L, 0, RM>(s, tid, u, bb)) {
+        d[s] = D[wrap(u + (L >> 1), L)];
+        b[s] = B[u];
+      }
     }
   }
   __device__ __forceinline__ float2 operator()(int slot, int u, int, int up) const {
-    const float2 g1 = cscale(cmul(R[up], ph), d[slot]);
-    return csub(A[up], rot_j(g1, (-u) & 3));
+    const float2 g0 = cscale(cmul(R[up], ph), d[slot]);
+    return csub(rot_j(g0, u & 3), b[slot]);
   }
 };
 
@@ -1148,32 +1153,28 @@ struct LoadPadded : NoPrefetch {
 };
 
 // Last pass of that FFT: x[u] = (C V)[u] + B[u], scaled by 1/sqrt(L), to the
-// symbol's subcarrier u.
-template <int IO, int NT, int L, int RM> struct StoreSubcarriers {
-  const float2* R; const float* D; float2 ph; typename Io<IO>::T* out; float scale;
-  float d[16];
-  __device__ __forceinline__ void prefetch(int tid) {
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int u = last_pos<NT, L, 0, RM>(s, tid);
-      if (u >= 0) d[s] = D[wrap(u + (L >> 1), L)];
-    }
-  }
-  __device__ __forceinline__ void operator()(int slot, int u, float2 v, int up) const {
-    const float2 b = rot_j(cscale(cmul(R[up], ph), d[slot]), (-u) & 3);
-    const float2 x = cadd(v, b);
+// symbol's subcarrier u (B from the task's scratch slot). Each B load waits
+// for the previous output store (the compiler cannot tell the two buffers
+// apart); fetching them ahead in registers cost the kernel its third wave
+// per SIMD and measured no faster.
+template <int IO, int NT, int L, int RM> struct StoreSubcarriers : NoPrefetch {
+  const float2* B; typename Io<IO>::T* out; float scale;
+  __device__ __forceinline__ void operator()(int, int u, float2 v, int) const {
+    const float2 x = cadd(v, B[u]);
     Io<IO>::st(out, u, make_float2(x.x * scale, x.y * scale));
   }
 };
 
 // Synchronised RX with OFDM demodulation in the simplified joint form of
-// Sec. V-A. Tasks hold whole symbols (block pairs). Per symbol: the first
+// Sec. V-A. Tasks hold whole symbols (block pairs). Per symbol: the second
 // block's long FFT is scattered into the subband regions and every subband
-// stores A[u] = g0[u] j^u in its second region (the same layout, above the
-// spectrum); the second block's long FFT is scattered likewise, then each
-// subband runs V = A - B -> IFFT -> keep the first half -> FFT -> + B in its
-// second region and writes the L subcarriers. Subbands with L <= 1024 run on
-// one wave (assignment as the RX kernel), longer ones on the workgroup.
+// stores B[u] = g1[u] (-j)^u in the task's scratch slot (global memory, so
+// that the regions are the only LDS and three workgroups fit a CU instead of
+// two); the first block's long FFT is scattered likewise, then each subband
+// runs V = A - B -> IFFT -> keep the first half -> FFT -> + B in place in its
+// region and writes the L subcarriers. Subbands with L <= 1024 run on one
+// wave (assignment as the RX kernel, the same wave storing and reading a
+// subband's B), longer ones on the workgroup.
 template <int IO, int NL, int TP>
 __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
   constexpr int RML = rx_long_cap(NL, TP);                 // long-FFT radix plan (transform plan TP)
@@ -1185,45 +1186,45 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
   const TaskDesc T = a.task[task];
   const GroupDesc G = a.grp[T.group];
   float2* S = smem;                                        // spectrum, then the block's regions
-  float2* Ab = smem + G.scr_off;                           // second regions (A, then V in place)
+  float2* Bt = reinterpret_cast<float2*>(a.part + T.part_off);   // the task's B terms
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = ((tid >> 6) + blockIdx.x) & 3;
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
   const uint64_t* map = a.rxmap + G.map_off;
   LoadAhead<IO, kThreads, NL, RML> lh;
   {
-    const BlockDesc B0 = a.blk[T.blk_first];
-    lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
+    const BlockDesc B1 = a.blk[T.blk_first + 1];
+    lh.issue(at<IO>(a.in, B1.t0), B1.hlo, B1.hhi, tid);
   }
   for (int bi = 0; bi + 1 < T.blk_count; bi += 2) {
     const BlockDesc B0 = a.blk[T.blk_first + bi];
     const BlockDesc B1 = a.blk[T.blk_first + bi + 1];
     StoreScatter sc;
     sc.S = S; sc.map = map;
-    // ---- first block: spectrum -> regions -> A
+    // ---- second block: spectrum -> regions -> B to the scratch slot
     __syncthreads();
     fft_run<kThreads, NL, 0, -1, RML>(S, tid, lh, sc, tw);
-    lh.issue(at<IO>(a.in, B1.t0), B1.hlo, B1.hhi, tid);
+    lh.issue(at<IO>(a.in, B0.t0), B0.hlo, B0.hhi, tid);
     __syncthreads();
     for (int m = 0; m < G.n_sb; ++m) {
       const SbDesc Sb = a.sb[G.sb_first + m];
       const bool mine = Sb.wave >= 0 ? Sb.wave == wave : true;
       if (!mine) continue;
       const int step = Sb.wave >= 0 ? 64 : kThreads;
-      const float2 ph = make_float2(a.bsb[B0.bs + m].ph.x, a.bsb[B0.bs + m].ph.y);
+      const float2 ph = make_float2(a.bsb[B1.bs + m].ph.x, a.bsb[B1.bs + m].ph.y);
       const float* D = a.weights + Sb.w_off;
       const float2* R = S + Sb.cofs;
-      float2* A = Ab + Sb.cofs;
-      for (int u = Sb.wave >= 0 ? lane : tid; u < Sb.L; u += step) {
-        const int up = pad(u);
-        A[up] = rot_j(cscale(cmul(R[up], ph), D[wrap(u + (Sb.L >> 1), Sb.L)]), u & 3);
-      }
+      float2* Bm = Bt + Sb.aofs;
+      for (int u = Sb.wave >= 0 ? lane : tid; u < Sb.L; u += step)
+        Bm[u] = rot_j(cscale(cmul(R[pad(u)], ph), D[wrap(u + (Sb.L >> 1), Sb.L)]), (-u) & 3);
     }
+    // (the barrier also orders the workgroup-wide subbands' B stores before
+    // their reads by other threads)
     __syncthreads();
-    // ---- second block: spectrum -> regions; per subband the joint transform
+    // ---- first block: spectrum -> regions; per subband the joint transform
     fft_run<kThreads, NL, 0, -1, RML>(S, tid, lh, sc, tw);
     if (bi + 2 < T.blk_count) {
-      const BlockDesc Bn = a.blk[T.blk_first + bi + 2];
+      const BlockDesc Bn = a.blk[T.blk_first + bi + 3];
       lh.issue(at<IO>(a.in, Bn.t0), Bn.hlo, Bn.hhi, tid);
     }
     __syncthreads();
@@ -1233,22 +1234,22 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
         for (int m = 0; m < G.n_sb; ++m) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave != wave) continue;
-          const BlockSb Z = a.bsb[B1.bs + m];
-          const float2 ph = make_float2(Z.ph.x, Z.ph.y);
-          float2* A = Ab + Sb.cofs;
+          float2* R = S + Sb.cofs;
+          const float2* Bm = Bt + Sb.aofs;
           constexpr int RMW = wave_radix_cap(LL);
           LoadV<64, LL, RMW> lv;
-          lv.A = A; lv.R = S + Sb.cofs; lv.D = a.weights + Sb.w_off; lv.ph = ph;
+          lv.R = R; lv.B = Bm; lv.D = a.weights + Sb.w_off;
+          lv.ph = make_float2(a.bsb[B0.bs + m].ph.x, a.bsb[B0.bs + m].ph.y);
           StoreMask sm;
-          sm.A = A; sm.half = LL / 2; sm.inv_l = 1.f / LL;
-          fft_run<64, LL, 0, +1, RMW>(A, lane, lv, sm, tw);
+          sm.A = R; sm.half = LL / 2; sm.inv_l = 1.f / LL;
+          fft_run<64, LL, 0, +1, RMW>(R, lane, lv, sm, tw);
           wave_sync();
           LoadPadded lp;
-          lp.A = A;
+          lp.A = R;
           StoreSubcarriers<IO, 64, LL, RMW> so;
-          so.R = S + Sb.cofs; so.D = a.weights + Sb.w_off; so.ph = ph; so.out = at<IO>(a.out, Z.x0);
+          so.B = Bm; so.out = at<IO>(a.out, a.bsb[B1.bs + m].x0);
           so.scale = rsqrtf((float)LL);
-          fft_run<64, LL, 0, -1, RMW>(A, lane, lp, so, tw);
+          fft_run<64, LL, 0, -1, RMW>(R, lane, lp, so, tw);
         }
       }
     };
@@ -1260,23 +1261,23 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
         for (int m = 0; m < G.n_sb; ++m) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave >= 0) continue;
-          const BlockSb Z = a.bsb[B1.bs + m];
-          const float2 ph = make_float2(Z.ph.x, Z.ph.y);
-          float2* A = Ab + Sb.cofs;
+          float2* R = S + Sb.cofs;
+          const float2* Bm = Bt + Sb.aofs;
           constexpr int RMG = radix_cap(LL);
           LoadV<kThreads, LL, RMG> lv;
-          lv.A = A; lv.R = S + Sb.cofs; lv.D = a.weights + Sb.w_off; lv.ph = ph;
+          lv.R = R; lv.B = Bm; lv.D = a.weights + Sb.w_off;
+          lv.ph = make_float2(a.bsb[B0.bs + m].ph.x, a.bsb[B0.bs + m].ph.y);
           StoreMask sm;
-          sm.A = A; sm.half = LL / 2; sm.inv_l = 1.f / LL;
+          sm.A = R; sm.half = LL / 2; sm.inv_l = 1.f / LL;
           __syncthreads();
-          fft_run<kThreads, LL, 0, +1, RMG>(A, tid, lv, sm, tw);
+          fft_run<kThreads, LL, 0, +1, RMG>(R, tid, lv, sm, tw);
           __syncthreads();
           LoadPadded lp;
-          lp.A = A;
+          lp.A = R;
           StoreSubcarriers<IO, kThreads, LL, RMG> so;
-          so.R = S + Sb.cofs; so.D = a.weights + Sb.w_off; so.ph = ph; so.out = at<IO>(a.out, Z.x0);
+          so.B = Bm; so.out = at<IO>(a.out, a.bsb[B1.bs + m].x0);
           so.scale = rsqrtf((float)LL);
-          fft_run<kThreads, LL, 0, -1, RMG>(A, tid, lp, so, tw);
+          fft_run<kThreads, LL, 0, -1, RMG>(R, tid, lp, so, tw);
         }
       }
     };

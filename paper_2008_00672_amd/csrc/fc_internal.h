@@ -160,7 +160,8 @@ struct SbDesc {
   int32_t w_off;          // offset of this subband's weights in the weight table
   int32_t wave;           // RX: wave (0..3) running this subband's short IFFT, -1: whole workgroup
   int32_t cofs;           // RX: LDS offset (complex entries) of this subband's region
-  int32_t aofs;           // weight gradient: offset (floats) of the subband's LDS accumulators
+  int32_t aofs;           // weight gradient: offset (floats) of the subband's LDS accumulators;
+                          // demodulating RX: complex offset of its terms in a task's slot
   int64_t lo_off;         // element offset of the subband's low-rate data for this op
   int64_t lo_len;         // number of low-rate samples for this op
 };
@@ -175,12 +176,14 @@ struct GroupDesc {
   int32_t scr_off;           // weight gradient: LDS offset (complex entries) of the short-FFT scratch
   int32_t wstride;           // weight gradient: scratch entries per wave (one-wave transforms)
   int32_t acc_off;           // weight gradient: LDS offset (complex entries) of the accumulators
-  int32_t acc_len;           // weight gradient: accumulator floats (sum of the subbands' L)
+  int32_t acc_len;           // weight gradient: accumulator floats (sum of the subbands' L);
+                             // demodulating RX: complex values of a task's scratch slot
   int32_t taper;             // TX, synchronised OLS: edge length T of the output windows (0: hard edges)
   int32_t wg_nb;             // weight gradient, one subband with L <= 1024: blocks per group (0: per block)
-  int32_t part_n;            // weight gradient: tasks of the group (partial-sum slots)
-  int64_t part_base;         // weight gradient: first float of the group's partial sums; the slot of
-                             // the group's i-th task (block order) starts at part_base + i * acc_len
+  int32_t part_n;            // tasks of the group (scratch slots)
+  int64_t part_base;         // first float of the group's scratch slots; the slot of the group's
+                             // i-th task (block order) starts at part_base + i * (slot floats:
+                             // acc_len for the weight gradient, 2 acc_len for the demodulating RX)
 };
 
 // One FC block of a group.
@@ -218,8 +221,10 @@ struct TaskDesc {
   int64_t z1_lo, z1_hi;
   int32_t ola;               // 1: blocks overlap-add their outputs (carry in LDS)
   int32_t accumulate;        // 1: out += value instead of out = value
-  int64_t part_off;          // weight gradient: this task's partial-sum slot (acc_len floats, in
-                             // fftshifted weight order per subband, at the subband's aofs)
+  int64_t part_off;          // this task's scratch slot in LaunchArgs::part. Weight gradient:
+                             // acc_len partial sums, in fftshifted weight order per subband at the
+                             // subband's aofs; demodulating RX: the second block's terms, L complex
+                             // values per subband at complex offset aofs
 };
 
 // Launch arguments of one kernel phase.
@@ -239,7 +244,7 @@ struct LaunchArgs {
   void* out;
   const void* in2;           // weight gradient: the forward low-rate input
   int32_t front;             // TX: 1 = input is the QAM grid (OFDM modulation in the kernel)
-  float* part;               // weight gradient: per-task partial sums (scratch)
+  float* part;               // per-task scratch (weight gradient, demodulating RX)
   int32_t tplan;             // transform plan (0 or 1, see pruned_ws / rx_long_cap)
 };
 

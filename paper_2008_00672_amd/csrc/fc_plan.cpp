@@ -86,7 +86,9 @@ struct Op {
   std::vector<BlockSb> bsb;
   std::vector<TaskDesc> task;
   std::vector<uint64_t> rxmap;            // RX scatter maps
-  int64_t part_total = 0;                 // adjoint op: floats of the weight gradient's partial sums
+  int64_t part_total = 0;                 // floats of per-task scratch: the weight gradient's partial
+                                          // sums, the demodulating RX's second-block terms
+  bool part_eager = false;                // scratch allocated with the tables (demodulating RX)
   // One kernel launch. kind: 0 = FC kernel of class cls (0 TX pruned, 1 TX
   // full, 2 RX / adjoint) and transform size `size`; 2 = zero the output
   // buffer. glds: LDS bytes of the weight-gradient kernel over the same tasks
@@ -101,7 +103,7 @@ struct Op {
   SbDesc* d_sb = nullptr; GroupDesc* d_grp = nullptr; BlockDesc* d_blk = nullptr;
   BlockSb* d_bsb = nullptr; TaskDesc* d_task = nullptr;
   uint64_t* d_rxmap = nullptr;
-  float* d_part = nullptr;                // weight-gradient scratch (allocated at its first use)
+  float* d_part = nullptr;                // per-task scratch (the weight gradient's at its first use)
 };
 
 }  // namespace
@@ -577,16 +579,20 @@ void build_op(fc_plan* P, int op_index) {
                     : P->run_len[kind] > 0 ? P->run_len[kind]
                                            : (int)std::max<int64_t>(2, std::min<int64_t>(8, total_blocks / 4096));
       if (kind == 3) K += K & 1;                        // whole symbols per task
-      // weight gradient: one partial-sum slot per task, in block order
+      // per-task scratch slots, in block order: the weight gradient's partial
+      // sums (one float per weight), the demodulating RX's second-block terms
+      // (one complex value per subband bin)
       GroupDesc& gw = op.grp[g];
+      const int64_t slot = wgrad ? gw.acc_len : kind == 3 ? 2 * (int64_t)gw.acc_len : 0;
       gw.part_base = op.part_total;
       gw.part_n = (nblk + K - 1) / K;
-      if (wgrad) op.part_total += (int64_t)gw.part_n * gw.acc_len;
+      op.part_total += (int64_t)gw.part_n * slot;
+      op.part_eager = kind == 3 && !wgrad;
       for (int b = 0; b < nblk; b += K) {
         TaskDesc t{};
         t.group = (int)g; t.blk_first = first_blk + b; t.blk_count = std::min(K, nblk - b);
         t.accumulate = acc ? 1 : 0;
-        t.part_off = gw.part_base + (int64_t)(b / K) * gw.acc_len;
+        t.part_off = gw.part_base + (int64_t)(b / K) * slot;
         PhaseTasks& ph = acc ? ((b & 1) ? rx_odd : rx_even) : rx_all;
         const GroupDesc& gd = op.grp[g];
         // adjoint: one-subband groups with a whole-workgroup short transform
@@ -595,9 +601,9 @@ void build_op(fc_plan* P, int op_index) {
         const bool greg = kind == 2 && gd.n_sb == 1 && gd.n_long_sb == 1;
         ClassTasks& ct = ph.cls[std::make_tuple(kind == 3 ? 4 : 2, N, greg ? 1 : 0)];
         ct.t.push_back(t);
-        // demodulating RX: a second set of subband regions holds the first
-        // block's spectra while the second block's long FFT runs
-        ct.lds = std::max(ct.lds, (size_t)(std::max(lds_elems(N), lsum) + (kind == 3 ? lsum : 0)) * 8);
+        // (the demodulating RX keeps its second-block terms in the task's
+        // scratch slot, so its LDS is the spectrum / subband regions as well)
+        ct.lds = std::max(ct.lds, (size_t)std::max(lds_elems(N), lsum) * 8);
         ct.glds = std::max(ct.glds, gd.wg_nb ? (size_t)wgg_lds_entries(lmax, N, gd.wg_nb) * 8
                                     : greg   ? (size_t)gd.acc_off * 8
                                              : (size_t)(gd.acc_off + (gd.acc_len + 1) / 2) * 8);
@@ -656,6 +662,11 @@ fc_status upload_op(Op& op) {
   if ((s = upload(op.bsb, &op.d_bsb))) return s;
   if ((s = upload(op.task, &op.d_task))) return s;
   if ((s = upload(op.rxmap, &op.d_rxmap))) return s;
+  if (op.part_eager && op.part_total > 0 &&
+      hipMalloc((void**)&op.d_part, (size_t)op.part_total * sizeof(float)) != hipSuccess) {
+    op.d_part = nullptr;
+    return FC_E_NOMEM;
+  }
   return FC_OK;
 }
 
@@ -674,7 +685,7 @@ hipError_t launch_phase(fc_plan* P, const Op& op, const Op::Phase& ph, const voi
   a.sb = op.d_sb; a.grp = op.d_grp; a.blk = op.d_blk; a.bsb = op.d_bsb;
   a.task = op.d_task + ph.first; a.n_task = ph.count; a.io = P->io;
   a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
-  a.in = in; a.out = out;
+  a.in = in; a.out = out; a.part = op.d_part;
   a.front = &op == &P->op[FC_OP_TXG] ? 1 : 0;
   const int k = (int)(&op - P->op);
   a.tplan = k < 5 ? P->tplan[k] : 0;

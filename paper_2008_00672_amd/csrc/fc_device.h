@@ -1116,24 +1116,25 @@ __device__ __forceinline__ float2 rot_j(float2 v, int k) {
 
 // First pass of the per-symbol IFFT, in place in the subband's region:
 // V[u] = A[u] - B[u] with A[u] = g0[u] j^u from the first block's spectrum
-// in the region and B[u] = g1[u] (-j)^u from the task's scratch slot, both
-// fetched before the pass.
-template <int NT, int L, int RM> struct LoadV {
+// in the region and B[u] = g1[u] (-j)^u stored after the second block (GB:
+// in device scratch at u, fetched with the weights before the pass; else in
+// LDS at the padded position).
+template <int NT, int L, int RM, bool GB> struct LoadV {
   const float2* R; const float2* B; const float* D; float2 ph;
-  float d[16]; float2 b[16];
+  float d[16]; float2 b[GB ? 16 : 1];
   __device__ __forceinline__ void prefetch(int tid) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       int u, bb;
       if (first_pos<NT, L, 0, RM>(s, tid, u, bb)) {
         d[s] = D[wrap(u + (L >> 1), L)];
-        b[s] = B[u];
+        if constexpr (GB) b[s] = B[u];
       }
     }
   }
   __device__ __forceinline__ float2 operator()(int slot, int u, int, int up) const {
     const float2 g0 = cscale(cmul(R[up], ph), d[slot]);
-    return csub(rot_j(g0, u & 3), b[slot]);
+    return csub(rot_j(g0, u & 3), GB ? b[GB ? slot : 0] : B[up]);
   }
 };
 
@@ -1153,14 +1154,14 @@ struct LoadPadded : NoPrefetch {
 };
 
 // Last pass of that FFT: x[u] = (C V)[u] + B[u], scaled by 1/sqrt(L), to the
-// symbol's subcarrier u (B from the task's scratch slot). Each B load waits
-// for the previous output store (the compiler cannot tell the two buffers
+// symbol's subcarrier u. With B in device scratch (GB) each B load waits for
+// the previous output store (the compiler cannot tell the two buffers
 // apart); fetching them ahead in registers cost the kernel its third wave
 // per SIMD and measured no faster.
-template <int IO, int NT, int L, int RM> struct StoreSubcarriers : NoPrefetch {
+template <int IO, int NT, int L, int RM, bool GB> struct StoreSubcarriers : NoPrefetch {
   const float2* B; typename Io<IO>::T* out; float scale;
-  __device__ __forceinline__ void operator()(int, int u, float2 v, int) const {
-    const float2 x = cadd(v, B[u]);
+  __device__ __forceinline__ void operator()(int, int u, float2 v, int up) const {
+    const float2 x = cadd(v, B[GB ? u : up]);
     Io<IO>::st(out, u, make_float2(x.x * scale, x.y * scale));
   }
 };
@@ -1168,15 +1169,17 @@ template <int IO, int NT, int L, int RM> struct StoreSubcarriers : NoPrefetch {
 // Synchronised RX with OFDM demodulation in the simplified joint form of
 // Sec. V-A. Tasks hold whole symbols (block pairs). Per symbol: the second
 // block's long FFT is scattered into the subband regions and every subband
-// stores B[u] = g1[u] (-j)^u in the task's scratch slot (global memory, so
-// that the regions are the only LDS and three workgroups fit a CU instead of
-// two); the first block's long FFT is scattered likewise, then each subband
-// runs V = A - B -> IFFT -> keep the first half -> FFT -> + B in place in its
-// region and writes the L subcarriers. Subbands with L <= 1024 run on one
-// wave (assignment as the RX kernel, the same wave storing and reading a
-// subband's B), longer ones on the workgroup.
-template <int IO, int NL, int TP>
-__global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
+// stores B[u] = g1[u] (-j)^u, in a second region set above the spectrum, or
+// (GB) in the task's scratch slot in device memory where the two sets would
+// cost workgroups per CU (the filter bank's regions take 38.5 KB: two sets
+// let two workgroups share a CU, one set three); the first block's long FFT
+// is scattered likewise, then each subband runs V = A - B -> IFFT -> keep the
+// first half -> FFT -> + B in place in its region and writes the L
+// subcarriers. Subbands with L <= 1024 run on one wave (assignment as the RX
+// kernel, the same wave storing and reading a subband's B), longer ones on
+// the workgroup.
+template <int IO, int NL, int TP, bool GB>
+__global__ __launch_bounds__(kThreads, rxd_waves_per_simd(IO)) void fc_rxd_kernel(LaunchArgs a, int) {
   constexpr int RML = rx_long_cap(NL, TP);                 // long-FFT radix plan (transform plan TP)
   extern __shared__ float2 smem[];
   const int n = gridDim.x;
@@ -1186,7 +1189,9 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
   const TaskDesc T = a.task[task];
   const GroupDesc G = a.grp[T.group];
   float2* S = smem;                                        // spectrum, then the block's regions
-  float2* Bt = reinterpret_cast<float2*>(a.part + T.part_off);   // the task's B terms
+  // B terms: the task's scratch slot (at aofs + u) or the second region set
+  // (at scr_off + cofs + pad(u))
+  float2* Bt = GB ? reinterpret_cast<float2*>(a.part + T.part_off) : smem + G.scr_off;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = ((tid >> 6) + blockIdx.x) & 3;
   const float2* tw = reinterpret_cast<const float2*>(a.twpass);
@@ -1214,9 +1219,9 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
       const float2 ph = make_float2(a.bsb[B1.bs + m].ph.x, a.bsb[B1.bs + m].ph.y);
       const float* D = a.weights + Sb.w_off;
       const float2* R = S + Sb.cofs;
-      float2* Bm = Bt + Sb.aofs;
+      float2* Bm = Bt + (GB ? Sb.aofs : Sb.cofs);
       for (int u = Sb.wave >= 0 ? lane : tid; u < Sb.L; u += step)
-        Bm[u] = rot_j(cscale(cmul(R[pad(u)], ph), D[wrap(u + (Sb.L >> 1), Sb.L)]), (-u) & 3);
+        Bm[GB ? u : pad(u)] = rot_j(cscale(cmul(R[pad(u)], ph), D[wrap(u + (Sb.L >> 1), Sb.L)]), (-u) & 3);
     }
     // (the barrier also orders the workgroup-wide subbands' B stores before
     // their reads by other threads)
@@ -1235,9 +1240,9 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave != wave) continue;
           float2* R = S + Sb.cofs;
-          const float2* Bm = Bt + Sb.aofs;
+          const float2* Bm = Bt + (GB ? Sb.aofs : Sb.cofs);
           constexpr int RMW = wave_radix_cap(LL);
-          LoadV<64, LL, RMW> lv;
+          LoadV<64, LL, RMW, GB> lv;
           lv.R = R; lv.B = Bm; lv.D = a.weights + Sb.w_off;
           lv.ph = make_float2(a.bsb[B0.bs + m].ph.x, a.bsb[B0.bs + m].ph.y);
           StoreMask sm;
@@ -1246,7 +1251,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
           wave_sync();
           LoadPadded lp;
           lp.A = R;
-          StoreSubcarriers<IO, 64, LL, RMW> so;
+          StoreSubcarriers<IO, 64, LL, RMW, GB> so;
           so.B = Bm; so.out = at<IO>(a.out, a.bsb[B1.bs + m].x0);
           so.scale = rsqrtf((float)LL);
           fft_run<64, LL, 0, -1, RMW>(R, lane, lp, so, tw);
@@ -1262,9 +1267,9 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
           const SbDesc Sb = a.sb[G.sb_first + m];
           if (Sb.L != LL || Sb.wave >= 0) continue;
           float2* R = S + Sb.cofs;
-          const float2* Bm = Bt + Sb.aofs;
+          const float2* Bm = Bt + (GB ? Sb.aofs : Sb.cofs);
           constexpr int RMG = radix_cap(LL);
-          LoadV<kThreads, LL, RMG> lv;
+          LoadV<kThreads, LL, RMG, GB> lv;
           lv.R = R; lv.B = Bm; lv.D = a.weights + Sb.w_off;
           lv.ph = make_float2(a.bsb[B0.bs + m].ph.x, a.bsb[B0.bs + m].ph.y);
           StoreMask sm;
@@ -1274,7 +1279,7 @@ __global__ __launch_bounds__(kThreads) void fc_rxd_kernel(LaunchArgs a, int) {
           __syncthreads();
           LoadPadded lp;
           lp.A = R;
-          StoreSubcarriers<IO, kThreads, LL, RMG> so;
+          StoreSubcarriers<IO, kThreads, LL, RMG, GB> so;
           so.B = Bm; so.out = at<IO>(a.out, a.bsb[B1.bs + m].x0);
           so.scale = rsqrtf((float)LL);
           fft_run<kThreads, LL, 0, -1, RMG>(R, tid, lp, so, tw);
@@ -1616,8 +1621,14 @@ hipError_t launch_size(int cls, const LaunchArgs& a, int aux, size_t lds, hipStr
   } else if (cls == 3) {
     hipLaunchKernelGGL((fc_wgrad_kernel<IO, SZ>), grid, block, lds, s, a, aux);
   } else if (cls == 4) {
-    if (alt && a.tplan) hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ, alt ? 1 : 0>), grid, block, lds, s, a, aux);
-    else hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ, 0>), grid, block, lds, s, a, aux);
+    // aux: 1 = the B terms in device scratch
+    if (aux) {
+      if (alt && a.tplan) hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ, alt ? 1 : 0, true>), grid, block, lds, s, a, aux);
+      else hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ, 0, true>), grid, block, lds, s, a, aux);
+    } else {
+      if (alt && a.tplan) hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ, alt ? 1 : 0, false>), grid, block, lds, s, a, aux);
+      else hipLaunchKernelGGL((fc_rxd_kernel<IO, SZ, 0, false>), grid, block, lds, s, a, aux);
+    }
   } else {
     if (alt && a.tplan) hipLaunchKernelGGL((fc_rx_kernel<IO, SZ, alt ? 1 : 0>), grid, block, lds, s, a, aux);
     else hipLaunchKernelGGL((fc_rx_kernel<IO, SZ, 0>), grid, block, lds, s, a, aux);
@@ -1678,10 +1689,12 @@ void lds_limits_size(size_t bytes, hipError_t& e) {
   grant_lds(fc_tx_full_kernel<IO, SZ, false>, bytes, e);
   grant_lds(fc_tx_full_kernel<IO, SZ, true>, bytes, e);
   grant_lds(fc_rx_kernel<IO, SZ, 0>, bytes, e);
-  grant_lds(fc_rxd_kernel<IO, SZ, 0>, bytes, e);
+  grant_lds(fc_rxd_kernel<IO, SZ, 0, false>, bytes, e);
+  grant_lds(fc_rxd_kernel<IO, SZ, 0, true>, bytes, e);
   if constexpr (rx_has_alt(SZ)) {
     grant_lds(fc_rx_kernel<IO, SZ, 1>, bytes, e);
-    grant_lds(fc_rxd_kernel<IO, SZ, 1>, bytes, e);
+    grant_lds(fc_rxd_kernel<IO, SZ, 1, false>, bytes, e);
+    grant_lds(fc_rxd_kernel<IO, SZ, 1, true>, bytes, e);
   }
   grant_lds(fc_wgrad_kernel<IO, SZ>, bytes, e);
 }

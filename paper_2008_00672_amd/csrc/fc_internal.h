@@ -68,6 +68,15 @@ constexpr int pruned_waves_per_simd(int L, int N, int tp = 0) {
   return 163840 / pruned_lds_bytes(L, N, tp) >= 3 ? 3 : 163840 / pruned_lds_bytes(L, N, tp);
 }
 
+// Demodulating RX: waves per SIMD that the kernel's register budget keeps
+// (its launch bounds). The second-block terms live in a second LDS region set
+// where the LDS of the two sets still lets that many workgroups share a CU
+// (a workgroup is one wave per SIMD), else in per-task device scratch.
+constexpr int rxd_waves_per_simd(int io) { return io == IO_C64 ? 2 : 3; }
+constexpr bool rxd_terms_in_lds(int io, int lds_two_sets_bytes) {
+  return 163840 / lds_two_sets_bytes >= rxd_waves_per_simd(io);
+}
+
 // Weight gradient of a one-subband group with L <= 1024, blocks in groups:
 // long-FFT buffer, then per block of a group its band region and its
 // short-FFT buffer (the per-bin sums are held in registers); the most of

@@ -583,7 +583,11 @@ void build_op(fc_plan* P, int op_index) {
       // sums (one float per weight), the demodulating RX's second-block terms
       // (one complex value per subband bin)
       GroupDesc& gw = op.grp[g];
-      const int64_t slot = wgrad ? gw.acc_len : kind == 3 ? 2 * (int64_t)gw.acc_len : 0;
+      // demodulating RX: the second-block terms in a second LDS region set
+      // where that keeps the kernel's occupancy, else in device scratch
+      const size_t lds_one = (size_t)std::max(lds_elems(N), lsum) * 8;
+      const bool gb = kind == 3 && !rxd_terms_in_lds(P->io, (int)(lds_one + (size_t)lsum * 8));
+      const int64_t slot = wgrad ? gw.acc_len : gb ? 2 * (int64_t)gw.acc_len : 0;
       gw.part_base = op.part_total;
       gw.part_n = (nblk + K - 1) / K;
       op.part_total += (int64_t)gw.part_n * slot;
@@ -599,11 +603,10 @@ void build_op(fc_plan* P, int op_index) {
         // get launches of their own, whose weight gradient keeps its sums in
         // registers (no LDS accumulators: one more workgroup per CU)
         const bool greg = kind == 2 && gd.n_sb == 1 && gd.n_long_sb == 1;
-        ClassTasks& ct = ph.cls[std::make_tuple(kind == 3 ? 4 : 2, N, greg ? 1 : 0)];
+        ClassTasks& ct = ph.cls[std::make_tuple(kind == 3 ? 4 : 2, N, (greg || gb) ? 1 : 0)];
         ct.t.push_back(t);
-        // (the demodulating RX keeps its second-block terms in the task's
-        // scratch slot, so its LDS is the spectrum / subband regions as well)
-        ct.lds = std::max(ct.lds, (size_t)std::max(lds_elems(N), lsum) * 8);
+        ct.aux = gb ? 1 : 0;
+        ct.lds = std::max(ct.lds, kind == 3 && !gb ? lds_one + (size_t)lsum * 8 : lds_one);
         ct.glds = std::max(ct.glds, gd.wg_nb ? (size_t)wgg_lds_entries(lmax, N, gd.wg_nb) * 8
                                     : greg   ? (size_t)gd.acc_off * 8
                                              : (size_t)(gd.acc_off + (gd.acc_len + 1) / 2) * 8);

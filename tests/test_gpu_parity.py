@@ -161,6 +161,30 @@ def test_rx_demod_filterbank(io):
     assert_gate(got, ref, io, "filterbank demod")
 
 
+# The demodulating RX keeps the second block's terms in a second LDS region
+# set, or in per-task device scratch where two sets would cost workgroups per
+# CU. Groups of 4224 region entries take two 33.8 KB sets: kept in LDS for
+# FP32 I/O (two workgroups per CU either way), in scratch for FP16 / BF16
+# (three with one set); the 2048-point subbands run on the workgroup, the
+# 1024-point ones on one wave each. four_long: three 2048-point subbands in
+# one group (two 50.7 KB sets: scratch for every I/O type) and one alone
+# (two 25.3 KB sets: LDS for every I/O type).
+TERMS = {
+    "wg_and_wave": [W.subband(30, 4, 1600, 8, 2048, 4096, -900, "sync_ols"),
+                    W.subband(30, 4, 800, 8, 1024, 4096, 700, "sync_ols"),
+                    W.subband(30, 4, 700, 8, 1024, 4096, 1500, "sync_ols")],
+    "four_long": DEMOD["four_long"],
+}
+
+
+@pytest.mark.parametrize("io", ["c64", "f16", "bf16"])
+@pytest.mark.parametrize("name", sorted(TERMS))
+def test_rx_demod_terms(name, io):
+    print("case: demodulating RX %s %s" % (name, io), flush=True)
+    got, ref = run_rx(TERMS[name], io, seed=29, weights="random", demod=True)
+    assert_gate(got, ref, io, name)
+
+
 @pytest.mark.parametrize("name", ["cont_ols_16_64", "cont_ola_16_64", "sync_ola_frac"])
 def test_adjoint_tiny(name):
     got, ref = run_rx(TINY_TX[name], "c64", seed=5, weights="random", adjoint=True)

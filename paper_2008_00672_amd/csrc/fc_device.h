@@ -768,13 +768,15 @@ template <int IO> struct LoadHigh : NoPrefetch {
 
 // RX short IFFT first pass from the subband's compacted region (bin u of the
 // subband at region[pad(u)], already in inverse-shift order), weighted by
-// D[p] and the conj phase; the transform then runs in place in the region.
+// D[p]; the transform then runs in place in the region. The block's conj
+// phase, one complex factor per block and subband, multiplies the kept
+// outputs instead (StoreLow: half of the L values for overlap 1/2).
 // The weights of this thread's first-pass bins are fetched when the transform
 // starts, together with its twiddle bases (their registers live only until
 // the first pass: the RX kernel keeps four waves per SIMD; 2 % off the RX
 // call against reading them at use).
 template <int NT, int L> struct LoadCompact {
-  const float2* R; const float* D; float2 ph;
+  const float2* R; const float* D;
   float d[16];
   __device__ __forceinline__ void prefetch(int tid) {
 #pragma unroll
@@ -785,15 +787,16 @@ template <int NT, int L> struct LoadCompact {
     }
   }
   __device__ __forceinline__ float2 operator()(int slot, int, int, int up) const {
-    return cscale(cmul(R[up], ph), d[slot]);
+    return cscale(R[up], d[slot]);
   }
 };
 
-// RX output: keep window [lo, hi) of the low-rate block.
+// RX output: keep window [lo, hi) of the low-rate block, times the block's
+// conj phase.
 template <int IO> struct StoreLow : NoPrefetch {
-  typename Io<IO>::T* out; int lo, hi; bool acc;
+  typename Io<IO>::T* out; int lo, hi; bool acc; float2 ph;
   __device__ __forceinline__ void operator()(int, int i, float2 v, int) const {
-    if (i >= lo && i < hi) put<IO>(out, i, v, acc);
+    if (i >= lo && i < hi) put<IO>(out, i, cmul(v, ph), acc);
   }
 };
 
@@ -1074,8 +1077,9 @@ __global__ __launch_bounds__(kThreads, IO == IO_C64 ? 3 : 4) void fc_rx_kernel(L
           const BlockSb Z = a.bsb[B.bs + m];
           StoreLow<IO> so;
           so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
+          so.ph = make_float2(Z.ph.x, Z.ph.y);
           LoadCompact<64, LL> lc2;
-          lc2.R = S + Sb.cofs; lc2.D = a.weights + Sb.w_off; lc2.ph = make_float2(Z.ph.x, Z.ph.y);
+          lc2.R = S + Sb.cofs; lc2.D = a.weights + Sb.w_off;
           fft_run<64, LL, 0, +1, wave_radix_cap(LL)>(S + Sb.cofs, lane, lc2, so, tw);
         }
       }
@@ -1091,8 +1095,9 @@ __global__ __launch_bounds__(kThreads, IO == IO_C64 ? 3 : 4) void fc_rx_kernel(L
           const BlockSb Z = a.bsb[B.bs + m];
           StoreLow<IO> so;
           so.out = at<IO>(a.out, Z.x0); so.lo = Z.lo; so.hi = Z.hi; so.acc = T.accumulate != 0;
+          so.ph = make_float2(Z.ph.x, Z.ph.y);
           LoadCompact<kThreads, LL> lc2;
-          lc2.R = S + Sb.cofs; lc2.D = a.weights + Sb.w_off; lc2.ph = make_float2(Z.ph.x, Z.ph.y);
+          lc2.R = S + Sb.cofs; lc2.D = a.weights + Sb.w_off;
           __syncthreads();
           fft_run<kThreads, LL, 0, +1, radix_cap(LL)>(S + Sb.cofs, tid, lc2, so, tw);
         }

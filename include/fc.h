@@ -300,10 +300,12 @@ fc_status fc_tx_adjoint(fc_plan* plan, const void* highrate_in, void* lowrate_ou
  * subbands), and a reduction adds every weight's slots in block order: the
  * summation tree is fixed, so the result is bitwise the same for every tuning
  * and every call. The scratch is allocated (hipMalloc) by the first call and
- * kept until fc_plan_destroy. Errors:
- * FC_E_ARG (null pointer), FC_E_STATE (host-only plan, or a plan with an
- * FC_SYNC_OLS subband, which has no adjoint), FC_E_NOMEM (scratch),
- * FC_E_DEVICE (launch failure).
+ * kept until fc_plan_destroy, so a graph capture (fc_graph_begin) may record
+ * this call only after one uncaptured call on the plan (or use
+ * fc_tx_weight_grad_noalloc). Errors:
+ * FC_E_ARG (null pointer), FC_E_STATE (host-only plan, a plan with an
+ * FC_SYNC_OLS subband, which has no adjoint, or a first call on a capturing
+ * stream), FC_E_NOMEM (scratch), FC_E_DEVICE (launch failure).
  */
 fc_status fc_tx_weight_grad(fc_plan* plan, const void* lowrate_in, const void* grad_out,
                             float* grad_w, void* stream);

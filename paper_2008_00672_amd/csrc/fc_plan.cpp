@@ -795,10 +795,16 @@ fc_status run_wgrad(fc_plan* P, const void* x, const void* g, float* grad_w, hip
   if (cur != P->device && hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
   fc_status r = FC_OK;
   // the partial sums live in plan-owned scratch, allocated at the first call
-  // after the adjoint's tasks were (re)built
-  if (!op.d_part && hipMalloc((void**)&op.d_part, (size_t)op.part_total * sizeof(float)) != hipSuccess) {
-    op.d_part = nullptr;
-    r = FC_E_NOMEM;
+  // after the adjoint's tasks were (re)built; not while the stream is being
+  // captured into a graph (an allocation there would fail the capture)
+  if (!op.d_part) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) r = FC_E_DEVICE;
+    else if (cs != hipStreamCaptureStatusNone) r = FC_E_STATE;
+    else if (hipMalloc((void**)&op.d_part, (size_t)op.part_total * sizeof(float)) != hipSuccess) {
+      op.d_part = nullptr;
+      r = FC_E_NOMEM;
+    }
   }
   if (r == FC_OK) r = launch_wgrad(P, x, g, grad_w, op.d_part, st);
   if (cur != P->device) (void)hipSetDevice(cur);

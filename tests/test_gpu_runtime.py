@@ -222,6 +222,47 @@ def test_graph_sees_new_weights():
     g.close()
 
 
+def test_graph_weight_grad_and_demod():
+    """The weight gradient's scratch is allocated by its first call, which a
+    capture refuses (FC_E_STATE, nothing recorded); after one eager call the
+    gradient and the demodulating RX (whose scratch comes with the plan) are
+    captured together and every replay equals the eager calls bit for bit."""
+    import torch
+    from paper_2008_00672_amd import Graph, OP_RXD
+    from paper_2008_00672_amd.fc import FcError
+    sbs, xs, Ds, p = _mixed()
+    x = to_device(_cat(xs), "c64")
+    _, lens, _ = stream_offsets(sbs)
+    rng = np.random.default_rng(6)
+    gy = to_device(rng.standard_normal(sum(lens)) + 1j * rng.standard_normal(sum(lens)), "c64")
+    gw = torch.empty(sum(sb["n_short"] for sb in sbs), dtype=torch.float32, device="cuda:0")
+    z = p.empty(int(p.layout(OP_RXD)[0][-1]))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with pytest.raises(FcError) as e:
+        with Graph(s):
+            p.weight_grad(x, gy, gw, stream=s)
+    print("first weight gradient under capture:", e.value, flush=True)
+    assert e.value.status == -6
+    gw_ref = p.weight_grad(x, gy).clone()
+    z_ref = p.rx_demod(gy).clone()
+    torch.cuda.synchronize()
+    with Graph(s) as g:
+        p.weight_grad(x, gy, gw, stream=s)
+        p.rx_demod(gy, z, stream=s)
+    for rep in range(3):
+        gw.fill_(float("nan"))
+        z.zero_()
+        torch.cuda.synchronize()
+        g.launch()
+        s.synchronize()
+        ok = torch.equal(gw, gw_ref) and torch.equal(z, z_ref)
+        print("replay %d equal %s" % (rep, ok), flush=True)
+        assert ok
+        (gw_ref * 2).sum().item()
+    g.close()
+
+
 @pytest.mark.parametrize("side_stream", [False, True], ids=["null_stream", "side_stream"])
 def test_autotune_keeps_results(side_stream):
     # On the null stream the candidates run eagerly; on another stream each is

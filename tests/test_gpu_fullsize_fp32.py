@@ -1,0 +1,99 @@
+"""Parity at the full sizes of the two FP32 throughput workloads that bench.py
+times, in its launch configuration (autotuned work split):
+
+* the plain single-subband form as one continuous burst of 4096 slots (24 PRB,
+  L = 512, N = 2048, continuous overlap-save, 50 % overlap, FP32 I/O). The
+  input repeats every slot and the block grid repeats with it, so from the
+  second slot on every slot's output equals the second one's bit for bit
+  (the first slot starts from the zero state before the burst). The burst's
+  start (first two slots) and end (last slot and the tail) are those of a
+  three-slot burst, which the oracle computes in full.
+* mixed numerology, 4000 one-subframe streams (15 kHz 48 PRB + 30 kHz 24 PRB
+  on 30.72 MS/s each), synchronised OLA TX, then the CP-removing RX of the
+  TX output. Every stream's output equals the first one's bit for bit; the
+  first stream's TX is checked against the oracle's TX, and its RX against
+  the oracle's RX of the same (GPU) TX output.
+Each comparison takes the FP32 L2 gate and the per-sample bound of
+fc_cases.assert_gate.
+"""
+import numpy as np
+import pytest
+
+from fc_cases import assert_gate, make_inputs, oracle_rx, oracle_tx, to_device
+from fcsynth import workloads as W
+from oracle import weights as ow
+
+pytestmark = pytest.mark.gpu
+
+BURST_SLOTS = 4096
+SUBFRAMES = 4000
+
+
+def _repeats(t, n_rep, n_each, start=0):
+    """The n_rep pieces of n_each samples of t from `start` equal the first
+    piece bit for bit."""
+    import torch
+    v = torch.view_as_real(t[start:start + n_rep * n_each]).contiguous().view(torch.int32).reshape(n_rep, -1)
+    return bool(torch.equal(v, v[:1].expand_as(v)))
+
+
+def test_plain_burst_full_size():
+    import torch
+    from paper_2008_00672_amd import OP_TX, Plan
+    print("case: plain FP32 burst, %d slots" % BURST_SLOTS, flush=True)
+    sbs, meta = W.plain_tx_slot()
+    s1 = sbs[0]
+    xs, _, _ = make_inputs([s1], meta["qam"], meta["seed"], "rc")
+    slot = xs[0]
+    p = Plan([dict(s1, n_symbols=14 * BURST_SLOTS)], io="c64", device=0)
+    lo, hi = p.layout(OP_TX)
+    x = to_device(slot, "c64").repeat(BURST_SLOTS).contiguous()
+    assert x.shape[0] == lo[-1]
+    y = p.empty(int(hi[-1]))
+    print("TX autotune:", p.autotune(OP_TX, x, y), flush=True)
+    y = p.tx(x, y)
+    torch.cuda.synchronize()
+    I = s1["n_long"] // s1["n_short"]
+    period = len(slot) * I                                   # high-rate samples per slot
+    n0 = I * s1["n_short"] * s1["overlap"][0] // s1["overlap"][1]   # first sample of x: I L_O
+    tail = int(hi[-1]) - (n0 + BURST_SLOTS * period)
+    assert _repeats(y, BURST_SLOTS - 2, period, start=n0 + period)
+    head = y[:n0 + 2 * period].cpu().numpy().astype(np.complex128)
+    end = y[-(period + tail):].cpu().numpy().astype(np.complex128)
+    del x, y
+    D = [ow.rc_weights(s1["n_short"], s1["n_active"], s1["n_tb"])]
+    y3 = oracle_tx([dict(s1, n_symbols=42)], [np.tile(slot, 3)], D)[0]
+    assert_gate([head], [y3[:len(head)]], "c64", "burst start")
+    assert_gate([end], [y3[-len(end):]], "c64", "burst end")
+
+
+def test_mixed_numerology_subframes_full_size():
+    import torch
+    from paper_2008_00672_amd import OP_RX, OP_TX, Plan
+    print("case: mixed numerology, %d subframes, TX + RX" % SUBFRAMES, flush=True)
+    sbs, meta = W.mixed_numerology("sync_ola")
+    allsb = [dict(s, stream=k) for k in range(SUBFRAMES) for s in sbs]
+    p = Plan(allsb, io="c64", device=0)
+    xs, Ds, _ = make_inputs(sbs, meta["qam"], meta["seed"], "rc")
+    x = to_device(np.concatenate(xs), "c64").repeat(SUBFRAMES).contiguous()
+    lo, hi = p.layout(OP_TX)
+    assert x.shape[0] == lo[-1]
+    y = p.empty(int(hi[-1]))
+    lo_r, _ = p.layout(OP_RX)
+    z = p.empty(int(lo_r[-1]))
+    print("TX autotune:", p.autotune(OP_TX, x, y), flush=True)
+    y = p.tx(x, y)
+    print("RX autotune:", p.autotune(OP_RX, y, z), flush=True)
+    z = p.rx(y, z)
+    torch.cuda.synchronize()
+    n_st = int(hi[1] - hi[0])                                 # high-rate samples per stream
+    n_rx = int(lo_r[len(sbs)])                                # low-rate samples per stream
+    assert _repeats(y, SUBFRAMES, n_st)
+    assert _repeats(z, SUBFRAMES, n_rx)
+    y0 = y[:n_st].cpu().numpy().astype(np.complex128)
+    z0 = z[:n_rx].cpu().numpy().astype(np.complex128)
+    del x, y, z
+    assert_gate([y0], oracle_tx(sbs, xs, Ds), "c64", "subframe TX")
+    ref = oracle_rx(sbs, [y0], Ds)
+    got = np.split(z0, np.cumsum([len(r) for r in ref])[:-1])
+    assert_gate(got, ref, "c64", "subframe RX of the TX output")

@@ -1,5 +1,6 @@
-"""Parity at the full sizes of the two FP32 throughput workloads that bench.py
-times, in its launch configuration (autotuned work split):
+"""Parity at the full sizes of the FP32 throughput workloads that bench.py
+times, in its launch configurations (autotuned work split where bench.py
+autotunes):
 
 * the plain single-subband form as one continuous burst of 4096 slots (24 PRB,
   L = 512, N = 2048, continuous overlap-save, 50 % overlap, FP32 I/O). The
@@ -13,13 +14,18 @@ times, in its launch configuration (autotuned work split):
   TX output. Every stream's output equals the first one's bit for bit; the
   first stream's TX is checked against the oracle's TX, and its RX against
   the oracle's RX of the same (GPU) TX output.
+* the 52-PRB full-band channel filter (L = N = 768 and 1024), 4096 slots as
+  streams, synchronised OLA TX and the demodulating RX of its output, in the
+  planner's default split (as bench.py times it): every stream bitwise equal
+  to the first, the first against the oracle (the RX against the oracle's
+  demodulating RX of the same TX output).
 Each comparison takes the FP32 L2 gate and the per-sample bound of
 fc_cases.assert_gate.
 """
 import numpy as np
 import pytest
 
-from fc_cases import assert_gate, make_inputs, oracle_rx, oracle_tx, to_device
+from fc_cases import assert_gate, make_inputs, oracle_rx, oracle_rxd, oracle_tx, to_device
 from fcsynth import workloads as W
 from oracle import weights as ow
 
@@ -27,6 +33,7 @@ pytestmark = pytest.mark.gpu
 
 BURST_SLOTS = 4096
 SUBFRAMES = 4000
+CF_SLOTS = 4096
 
 
 def _repeats(t, n_rep, n_each, start=0):
@@ -97,3 +104,29 @@ def test_mixed_numerology_subframes_full_size():
     ref = oracle_rx(sbs, [y0], Ds)
     got = np.split(z0, np.cumsum([len(r) for r in ref])[:-1])
     assert_gate(got, ref, "c64", "subframe RX of the TX output")
+
+
+@pytest.mark.parametrize("n", [768, 1024])
+def test_channel_filter_full_size(n):
+    import torch
+    from paper_2008_00672_amd import OP_RXD, OP_TX, Plan
+    print("case: channel filter L = N = %d, %d slots" % (n, CF_SLOTS), flush=True)
+    sb1, meta = W.wideband_slot("sync_ola", n)
+    p = Plan([dict(sb1[0], stream=k) for k in range(CF_SLOTS)], io="c64", device=0)
+    xs, Ds, _ = make_inputs(sb1, meta["qam"], meta["seed"], "rc")
+    x = to_device(xs[0], "c64").repeat(CF_SLOTS).contiguous()
+    lo, hi = p.layout(OP_TX)
+    assert x.shape[0] == lo[-1]
+    y = p.tx(x)
+    z = p.rx_demod(y)
+    torch.cuda.synchronize()
+    n_st = int(hi[1] - hi[0])
+    n_z = int(p.layout(OP_RXD)[0][1])
+    assert n_z == 14 * n
+    assert _repeats(y, CF_SLOTS, n_st)
+    assert _repeats(z, CF_SLOTS, n_z)
+    y0 = y[:n_st].cpu().numpy().astype(np.complex128)
+    z0 = z[:n_z].cpu().numpy().astype(np.complex128)
+    del x, y, z
+    assert_gate([y0], oracle_tx(sb1, xs, Ds), "c64", "channel filter TX")
+    assert_gate([z0], oracle_rxd(sb1, [y0], Ds), "c64", "channel filter demodulating RX of the TX output")

@@ -1,0 +1,135 @@
+"""The host planner under AddressSanitizer (CPU only, no GPU code is
+instrumented): fc_plan.cpp is rebuilt with -fsanitize=address on the host
+side and linked, with the library's other objects as built, into a C++
+driver that creates host-only plans (device = -1) for a few hundred seeded
+random configurations (valid and invalid: every mode, power-of-two and
+mixed-radix sizes, sizes the library rejects, one to six subbands on one or
+two streams, explicit CP schedules, tapers) and reads every layout, CP
+schedule and statistic, retunes every operation and destroys the plan. Any
+out-of-bounds access, use after free or leak in the planner fails the run.
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_2008_00672_amd")
+BUILD = os.path.join(PKG, "_build")
+
+DRIVER = r"""
+#include "fc.h"
+#include <stdint.h>
+#include <stdio.h>
+
+static uint64_t rs = 88172645463325252ull;
+static uint32_t rnd(uint32_t n) {            /* xorshift64 */
+  rs ^= rs << 13; rs ^= rs >> 7; rs ^= rs << 17;
+  return (uint32_t)(rs % n);
+}
+
+int main() {
+  const int sizes[] = {16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 768, 1536, 3072, 96, 8192};
+  const int modes[] = {FC_CONT_OLA, FC_CONT_OLS, FC_SYNC_OLA, FC_SYNC_OLS};
+  int ok = 0, rejected = 0;
+  for (int it = 0; it < 400; ++it) {
+    /* three in four draws keep to the validity rules (one stream, one
+       numerology, n_long / n_short a power of two, K even, the band inside
+       both transforms); the rest draw every field freely */
+    const bool lean = rnd(4) != 0;
+    const int nsb = 1 + (int)rnd(lean ? 4 : 6);
+    fc_subband sb[6] = {};
+    int32_t ncp[6][32];
+    const int mode = modes[rnd(4)];
+    const int scs = 15 << rnd(3);
+    const int nsym = 1 + (int)rnd(20);
+    const int N0 = lean ? (256 << rnd(5)) : sizes[rnd(12)];
+    for (int m = 0; m < nsb; ++m) {
+      int L, N;
+      if (lean) {
+        N = N0;
+        L = rnd(8) ? N >> rnd(4) : (N >= 1024 ? 3 * (N >> (2 + rnd(2))) : N);
+        if (L > N || L < 16) L = N;
+      } else {
+        L = rnd(3) ? sizes[rnd(14)] : N0;
+        N = rnd(4) ? N0 : L * (1 << rnd(4));
+      }
+      sb[m].scs_khz = scs;
+      sb[m].n_symbols = nsym;
+      sb[m].n_short = L;
+      sb[m].n_long = N;
+      sb[m].n_tb = (int)rnd(lean ? 5 : 10);
+      const int kmax = L - 2 * sb[m].n_tb - 2;
+      sb[m].n_active = lean ? (kmax >= 2 ? 2 * (int)rnd((uint32_t)(kmax / 2)) : 0)   /* K even */
+                            : (L > 0 ? (int)rnd((uint32_t)L) : 0);
+      const int cmax = N / 2 - L / 2;
+      sb[m].center_bin = lean ? (cmax > 0 ? (int)rnd((uint32_t)(2 * cmax + 1)) - cmax : 0)
+                              : (N > 0 ? (int)rnd((uint32_t)N) - N / 2 : 0);
+      sb[m].overlap_num = 1;
+      sb[m].overlap_den = rnd(4) ? 2 : 4;
+      sb[m].mode = mode;
+      sb[m].stream = (!lean && nsb > 1) ? (int)rnd(2) : 0;
+      sb[m].taper = (mode == FC_SYNC_OLS && rnd(2)) ? 2 * (int)rnd(16) : 0;
+      if (!lean && rnd(4) == 0) {
+        for (int k = 0; k < 32; ++k) ncp[m][k] = (int)rnd((uint32_t)(N / 4 + 1));
+        sb[m].ncp_high = ncp[m];
+      }
+    }
+    fc_plan* p = 0;
+    const fc_status s = fc_plan_create(sb, nsb, (int)rnd(3), -1, &p);
+    if (s != FC_OK) {
+      if (p) return 10;
+      ++rejected;
+      continue;
+    }
+    ++ok;
+    int32_t n_sb = 0, n_st = 0;
+    if (fc_plan_counts(p, &n_sb, &n_st) != FC_OK || n_sb != nsb) return 11;
+    int64_t lo[7], hi[3], a, b, c;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int op = 0; op < 5; ++op) {
+        if (fc_plan_layout(p, op, lo, hi) == FC_OK) {
+          for (int m = 0; m < nsb; ++m)
+            if (lo[m + 1] < lo[m]) return 12;
+        }
+        (void)fc_plan_stats(p, op, &a, &b, &c);
+        if (pass == 0) {
+          (void)fc_plan_set_tuning(p, op, 2 * (int)rnd(9), 1 + (int)rnd(4));
+          (void)fc_plan_set_transform_plan(p, op, (int)rnd(2));
+        }
+      }
+    }
+    int32_t nh[32], nl[32];
+    int64_t off;
+    for (int m = 0; m < nsb; ++m)
+      if (fc_plan_symbols(p, m, nh, nl, &off) != FC_OK) return 13;
+    fc_plan_destroy(p);
+  }
+  printf("plans %d rejected %d\n", ok, rejected);
+  return ok >= 100 && rejected >= 40 ? 0 : 20;
+}
+"""
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(BUILD, "0_fc_kern_io.o")), reason="library objects not built")
+@pytest.mark.skipif(shutil.which("/opt/rocm/bin/hipcc") is None, reason="no hipcc")
+def test_planner_under_asan(tmp_path):
+    from paper_2008_00672_amd import build as B
+    objs = sorted(f for f in os.listdir(BUILD) if f.endswith(".o") and "fc_plan" not in f)
+    assert len(objs) == len(B.UNITS) - 1, objs
+    base = [B.hipcc(), "-O1", "-g", "-std=c++17", "--offload-arch=gfx950", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-fsanitize=address", "-I", os.path.join(ROOT, "include")]
+    plan_o = str(tmp_path / "fc_plan_asan.o")
+    drv = tmp_path / "driver.cpp"
+    drv.write_text(DRIVER)
+    drv_o = str(tmp_path / "driver.o")
+    exe = str(tmp_path / "driver")
+    subprocess.run(base + ["-c", "-o", plan_o, os.path.join(PKG, "csrc", "fc_plan.cpp")], check=True)
+    subprocess.run(base + ["-c", "-o", drv_o, str(drv)], check=True)
+    subprocess.run(base + ["-o", exe, drv_o, plan_o] + [os.path.join(BUILD, f) for f in objs], check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=42")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    print(r.stdout[-2000:], r.stderr[-4000:])
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert "AddressSanitizer" not in r.stderr and "LeakSanitizer" not in r.stderr

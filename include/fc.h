@@ -394,7 +394,8 @@ fc_status fc_plan_autotune(fc_plan* plan, int32_t op, const void* in, void* out,
 /*
  * HIP graphs of FC calls. fc_graph_begin starts a capture of `stream` (not
  * the legacy null stream); every fc_* call issued on it until fc_graph_end
- * is recorded (kernel launches, fills, fork/join of the side streams; none
+ * is recorded (issue the calls on `stream` itself: calls issued on other
+ * streams that joined the capture through events are not supported) (kernel launches, fills, fork/join of the side streams; none
  * allocates or synchronises), and fc_graph_end instantiates the graph.
  * fc_graph_launch replays it on any stream. Plans and buffers are recorded
  * by address and must outlive the graph, and so must the plans' work tables:

@@ -365,12 +365,18 @@ fc_status fc_plan_get_tuning(const fc_plan* plan, int32_t op, int32_t* run_len, 
  * n_long = 4096, radix 4 at 2048). Elsewhere both plans are the same kernel.
  * Plan 1 changes the order of the FP32 operations, so results differ from
  * plan 0 by rounding. Set like fc_plan_set_tuning (device idle, tables
- * rebuilt, graphs must be captured again); fc_plan_autotune also chooses it.
- * Errors: FC_E_ARG (op or plan out of range), FC_E_STATE, FC_E_NOMEM,
- * FC_E_DEVICE.
+ * rebuilt, graphs must be captured again); setting it applies to every
+ * kernel class of the op. fc_plan_autotune chooses it too, and then, kernel
+ * class by kernel class (one launch per class), the other plan where that
+ * makes the whole call faster; fc_plan_get_transform_plan returns the op's
+ * plan, fc_plan_get_class_plans how many of the op's kernel classes have two
+ * plans (*n_classes) and how many of those run plan 1 (*n_plan1).
+ * Errors: FC_E_ARG (op or plan out of range, NULL result pointer),
+ * FC_E_STATE, FC_E_NOMEM, FC_E_DEVICE.
  */
 fc_status fc_plan_set_transform_plan(fc_plan* plan, int32_t op, int32_t tplan);
 fc_status fc_plan_get_transform_plan(const fc_plan* plan, int32_t op, int32_t* tplan);
+fc_status fc_plan_get_class_plans(const fc_plan* plan, int32_t op, int32_t* n_classes, int32_t* n_plan1);
 
 /*
  * Autotuner: times op on the caller's buffers (in / out as for the op's
@@ -383,10 +389,12 @@ fc_status fc_plan_get_transform_plan(const fc_plan* plan, int32_t op, int32_t* t
  * launch gaps do not enter the choice), then applies the
  * fastest. With conc > 1 it first times every kernel launch of the op on its
  * own and spreads the launches over the streams longest first by those
- * measured times (kept until the next fc_plan_set_tuning). Synchronous. The
- * chosen values and time per call (ms) are written to the non-NULL result
- * pointers; the chosen transform plan is read back with
- * fc_plan_get_transform_plan.
+ * measured times (kept until the next fc_plan_set_tuning). Last, class by
+ * class (largest first), it keeps the other transform plan for a kernel
+ * class where the whole call then times at least 0.5 % faster. Synchronous.
+ * The chosen values and time per call (ms) are written to the non-NULL
+ * result pointers; the chosen transform plans are read back with
+ * fc_plan_get_transform_plan and fc_plan_get_class_plans.
  */
 fc_status fc_plan_autotune(fc_plan* plan, int32_t op, const void* in, void* out, void* stream,
                            int32_t* best_run_len, int32_t* best_conc, float* best_ms);
@@ -394,9 +402,10 @@ fc_status fc_plan_autotune(fc_plan* plan, int32_t op, const void* in, void* out,
 /*
  * HIP graphs of FC calls. fc_graph_begin starts a capture of `stream` (not
  * the legacy null stream); every fc_* call issued on it until fc_graph_end
- * is recorded (issue the calls on `stream` itself: calls issued on other
- * streams that joined the capture through events are not supported) (kernel launches, fills, fork/join of the side streams; none
+ * is recorded (kernel launches, fills, fork/join of the side streams; none
  * allocates or synchronises), and fc_graph_end instantiates the graph.
+ * Issue the calls on `stream` itself: calls issued on other streams that
+ * joined the capture through events are not supported.
  * fc_graph_launch replays it on any stream. Plans and buffers are recorded
  * by address and must outlive the graph, and so must the plans' work tables:
  * fc_plan_set_tuning and fc_plan_autotune rebuild them, so capture after

@@ -97,6 +97,8 @@ struct Op {
   struct Phase {
     int kind; int first, count; size_t lds; int aux; int64_t zero_n; int cls, size; size_t glds;
     int seq; double cost;
+    int key3;      // third element of the class key (cls, size, key3)
+    int tplan;     // transform plan of the launch
   };
   std::vector<Phase> phases;
   // device copies
@@ -131,6 +133,9 @@ struct fc_plan {
   Op op[kOps];                        // FC_OP_TX .. FC_OP_TXG, then the weight gradient's schedule
   int run_len[5] = {0, 0, 0, 0, 0};   // blocks per task per op (0: planner heuristic)
   int tplan[5] = {0, 0, 0, 0, 0};     // transform plan per op (0 or 1: pruned_ws, rx_long_cap)
+  // per-class exceptions to tplan (kernel class key -> plan), chosen by the
+  // autotuner; cleared by fc_plan_set_transform_plan
+  std::map<std::tuple<int, int, int>, int> class_tp[5];
   int conc[5] = {kMaxConc, kMaxConc, kMaxConc, kMaxConc, kMaxConc};   // per op: launches of one independent set in flight
   hipStream_t side[kMaxConc - 1] = {};
   hipEvent_t ev_fork = nullptr;
@@ -254,6 +259,14 @@ Win clip_valid(const Sub& s, int64_t xrel, int lo, int hi, int64_t len) {
   int64_t a = std::max<int64_t>(lo, -xrel), b = std::min<int64_t>(hi, len - xrel);
   if (b < a) b = a;
   return Win{xrel, (int)a, (int)b};
+}
+
+// Transform plan of the kernel class `key` of op op_index: the autotuner's
+// per-class choice where it made one, else the op's plan.
+int class_plan(const fc_plan* P, int op_index, const std::tuple<int, int, int>& key) {
+  if (op_index >= 5) return 0;
+  const auto it = P->class_tp[op_index].find(key);
+  return it != P->class_tp[op_index].end() ? it->second : P->tplan[op_index];
 }
 
 void build_op(fc_plan* P, int op_index) {
@@ -560,7 +573,7 @@ void build_op(fc_plan* P, int op_index) {
         if (gd.prune) {
           ct.aux = ilog2(s0.I);
           // long IFFT buffer, OLA carry, and (L <= 1024) the short-FFT / band regions
-          ct.lds = std::max(ct.lds, (size_t)pruned_lds_bytes(s0.L, N, P->tplan[kind]));
+          ct.lds = std::max(ct.lds, (size_t)pruned_lds_bytes(s0.L, N, class_plan(P, op_index, key)));
         } else {
           ct.aux = std::max(ct.aux, lmax);
           ct.lds = std::max(ct.lds, (size_t)(lds_elems(N) + lds_elems(ct.aux) + N / 2) * 8);
@@ -637,7 +650,8 @@ void build_op(fc_plan* P, int op_index) {
       double cost = 0;
       for (const TaskDesc& t : ct.t) cost += (double)op.grp[t.group].N * t.blk_count;
       Op::Phase p{0, (int)op.task.size(), (int)ct.t.size(), ct.lds, ct.aux, 0, std::get<0>(kv.first),
-                  std::get<1>(kv.first), ct.glds, seq, cost};
+                  std::get<1>(kv.first), ct.glds, seq, cost, std::get<2>(kv.first),
+                  class_plan(P, op_index, kv.first)};
       op.task.insert(op.task.end(), ct.t.begin(), ct.t.end());
       op.phases.push_back(p);
     }
@@ -690,8 +704,7 @@ hipError_t launch_phase(fc_plan* P, const Op& op, const Op::Phase& ph, const voi
   a.weights = P->d_w; a.twiddle = P->d_tw; a.twpass = P->d_twp; a.rxmap = op.d_rxmap;
   a.in = in; a.out = out; a.part = op.d_part;
   a.front = &op == &P->op[FC_OP_TXG] ? 1 : 0;
-  const int k = (int)(&op - P->op);
-  a.tplan = k < 5 ? P->tplan[k] : 0;
+  a.tplan = ph.tplan;
   return launch_kernel(ph.cls, ph.size, a, ph.aux, ph.lds, st);
 }
 
@@ -1129,12 +1142,29 @@ fc_status fc_plan_set_transform_plan(fc_plan* P, int32_t op, int32_t tplan) {
     if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(P->device) != hipSuccess) return FC_E_DEVICE;
     const bool ok = hipDeviceSynchronize() == hipSuccess;
     P->tplan[op] = tplan;
+    P->class_tp[op].clear();
     const fc_status st = ok ? rebuild_op(P, op) : FC_E_DEVICE;
     (void)hipSetDevice(cur);
     return st;
   }
   P->tplan[op] = tplan;
+  P->class_tp[op].clear();
   return rebuild_op(P, op);
+}
+
+fc_status fc_plan_get_class_plans(const fc_plan* P, int32_t op, int32_t* n_classes, int32_t* n_plan1) {
+  if (!P || op < 0 || op > 4 || !n_classes || !n_plan1) return FC_E_ARG;
+  if (!P->op[op].valid) return FC_E_STATE;
+  *n_classes = 0;
+  *n_plan1 = 0;
+  for (const auto& ph : P->op[op].phases) {
+    if (ph.kind == 2) continue;
+    const bool alt = (ph.cls == 0 && pruned_has_alt(ph.size)) || ((ph.cls == 2 || ph.cls == 4) && rx_has_alt(ph.size));
+    if (!alt) continue;
+    ++*n_classes;
+    if (ph.tplan == 1) ++*n_plan1;
+  }
+  return FC_OK;
 }
 
 fc_status fc_plan_get_transform_plan(const fc_plan* P, int32_t op, int32_t* tplan) {
@@ -1203,6 +1233,8 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
   float best = 1e30f;
   int b_len = P->run_len[op], b_conc = P->conc[op], b_tp = P->tplan[op];
   const int n_tp = has_second_plan(P, op) ? 2 : 1;
+  const auto saved_classes = P->class_tp[op];
+  P->class_tp[op].clear();
   for (int tp = 0; tp < n_tp && result == FC_OK; ++tp) {
     P->tplan[op] = tp;                     // applied by the rebuilds of set_tuning below
     for (int conc : {1, kMaxConc}) {
@@ -1217,8 +1249,35 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
     }
   }
   P->tplan[op] = b_tp;
+  if (result != FC_OK) P->class_tp[op] = saved_classes;
   if (result == FC_OK) result = fc_plan_set_tuning(P, op, b_len, b_conc);
   if (result == FC_OK && b_conc > 1) result = measure_costs(P, op, in, out, st, e0, e1);
+  // then, class by class (largest first), the other transform plan where it
+  // makes the whole call faster by more than the timing noise: the classes
+  // share the GPU, so each change is judged on the call, not on the class
+  if (result == FC_OK && n_tp == 2) {
+    std::vector<std::tuple<int, int, int>> keys;
+    for (const auto& ph : P->op[op].phases) {
+      if (ph.kind == 2) continue;
+      const bool alt = (ph.cls == 0 && pruned_has_alt(ph.size)) || ((ph.cls == 2 || ph.cls == 4) && rx_has_alt(ph.size));
+      const auto key = std::make_tuple(ph.cls, ph.size, ph.key3);
+      if (alt && std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
+    }
+    float cur = 1e30f;
+    result = time_op(P, op, in, out, st, e0, e1, &cur);
+    for (size_t i = 0; i < keys.size() && result == FC_OK; ++i) {
+      P->class_tp[op][keys[i]] = 1 - b_tp;
+      if ((result = fc_plan_set_tuning(P, op, b_len, b_conc)) != FC_OK) break;
+      if (b_conc > 1 && (result = measure_costs(P, op, in, out, st, e0, e1)) != FC_OK) break;
+      float t = 1e30f;
+      if ((result = time_op(P, op, in, out, st, e0, e1, &t)) != FC_OK) break;
+      if (t < 0.995f * cur) cur = t;
+      else P->class_tp[op].erase(keys[i]);
+    }
+    if (result == FC_OK) result = fc_plan_set_tuning(P, op, b_len, b_conc);
+    if (result == FC_OK && b_conc > 1) result = measure_costs(P, op, in, out, st, e0, e1);
+    if (result == FC_OK) best = cur;
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipSetDevice(cur);

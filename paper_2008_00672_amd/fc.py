@@ -54,6 +54,7 @@ EXPORTS = {
     "fc_plan_get_tuning": (_I32, [_P, _I32, _I32P, _I32P]),
     "fc_plan_set_transform_plan": (_I32, [_P, _I32, _I32]),
     "fc_plan_get_transform_plan": (_I32, [_P, _I32, _I32P]),
+    "fc_plan_get_class_plans": (_I32, [_P, _I32, _I32P, _I32P]),
     "fc_plan_autotune": (_I32, [_P, _I32, _P, _P, _P, _I32P, _I32P, ctypes.POINTER(ctypes.c_float)]),
     "fc_graph_begin": (_I32, [_P]),
     "fc_graph_end": (_I32, [_P, ctypes.POINTER(_P)]),
@@ -334,6 +335,13 @@ class Plan:
         _check(lib().fc_plan_get_transform_plan(self._h, op, ctypes.byref(t)), "fc_plan_get_transform_plan")
         return t.value
 
+    def get_class_plans(self, op):
+        """(kernel classes of op with two transform plans, how many run plan 1)."""
+        n, n1 = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fc_plan_get_class_plans(self._h, op, ctypes.byref(n), ctypes.byref(n1)),
+               "fc_plan_get_class_plans")
+        return n.value, n1.value
+
     def autotune(self, op, inp, out, stream=None):
         """Time the op's work splits and transform plans on these buffers (out
         is overwritten) and keep the fastest; returns the choice and its time
@@ -345,7 +353,9 @@ class Plan:
         r, c, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
         _check(lib().fc_plan_autotune(self._h, op, _ptr(inp), _ptr(out), _stream_handle(stream), ctypes.byref(r),
                                       ctypes.byref(c), ctypes.byref(ms)), "fc_plan_autotune")
-        return dict(run_len=r.value, conc=c.value, plan=self.get_transform_plan(op), ms=ms.value)
+        n, n1 = self.get_class_plans(op)
+        return dict(run_len=r.value, conc=c.value, plan=self.get_transform_plan(op), classes_plan1=n1,
+                    classes_two_plans=n, ms=ms.value)
 
 
 class Graph:

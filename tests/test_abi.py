@@ -212,16 +212,21 @@ def test_tuning_host_plan():
 
 
 def test_transform_plan_host_plan():
-    """Transform plans 0/1 per op: set, read back, the blocks unchanged;
-    out-of-range values rejected."""
+    """Transform plans 0/1 per op: set, read back (op and per-class counts),
+    the blocks unchanged; out-of-range values rejected."""
     fc = _lib()
     sbs, _ = W.batched_carriers(n_carriers=8)
     p = _plan(sbs, io="f16")
     base = p.stats(fc.OP_TX)
     for op in (fc.OP_TX, fc.OP_RX, fc.OP_ADJ, fc.OP_RXD, fc.OP_TXG):
         assert p.get_transform_plan(op) == 0
+        n, n1 = p.get_class_plans(op)
+        assert 0 <= n and n1 == 0
         p.set_transform_plan(op, 1)
         assert p.get_transform_plan(op) == 1
+        assert p.get_class_plans(op) == (n, n)      # every class with two plans now runs plan 1
+    # the 8 carriers' pruned TX classes with n_short <= 1024 have two plans
+    assert p.get_class_plans(fc.OP_TX)[0] > 0
     assert p.stats(fc.OP_TX)["blocks"] == base["blocks"]
     for bad in (-1, 2):
         with pytest.raises(fc.FcError, match="invalid argument"):

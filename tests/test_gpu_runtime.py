@@ -280,10 +280,11 @@ def test_autotune_keeps_results(side_stream):
     assert best["run_len"] in (0, 8, 16, 32, 64) and best["conc"] in (1, 4) and best["plan"] in (0, 1)
     assert best["ms"] > 0
     assert p.get_tuning(OP_TX) == dict(run_len=best["run_len"], conc=best["conc"])
+    assert (best["classes_two_plans"], best["classes_plan1"]) == p.get_class_plans(OP_TX)
     y = p.tx(x, stream=s)
     torch.cuda.synchronize()
-    if best["plan"] == 0:
-        assert torch.equal(y, ref)           # same transform plan: the same bits
+    if best["classes_plan1"] == 0:
+        assert torch.equal(y, ref)           # every class on plan 0: the same bits
     else:                                    # the other plan rounds differently
         from fc_cases import assert_gate
         f, g = y.to(torch.float32).cpu().numpy(), ref.to(torch.float32).cpu().numpy()

@@ -168,12 +168,18 @@ def test_rx_demod_filterbank(io):
 # (three with one set); the 2048-point subbands run on the workgroup, the
 # 1024-point ones on one wave each. four_long: three 2048-point subbands in
 # one group (two 50.7 KB sets: scratch for every I/O type) and one alone
-# (two 25.3 KB sets: LDS for every I/O type).
+# (two 25.3 KB sets: LDS for every I/O type). tri_768 / tri_1536: the same
+# choices for mixed-radix sizes.
 TERMS = {
     "wg_and_wave": [W.subband(30, 4, 1600, 8, 2048, 4096, -900, "sync_ols"),
                     W.subband(30, 4, 800, 8, 1024, 4096, 700, "sync_ols"),
                     W.subband(30, 4, 700, 8, 1024, 4096, 1500, "sync_ols")],
     "four_long": DEMOD["four_long"],
+    # mixed-radix subbands: five 768-point ones on the waves (two 31.7 KB
+    # sets: LDS for FP32, scratch for FP16 / BF16) and four 1536-point ones
+    # on the workgroup (two 50.7 KB sets: scratch for every storage type)
+    "tri_768": [W.subband(15, 2, 600, 8, 768, 3072, c, "sync_ols") for c in (-1000, -500, 0, 500, 1000)],
+    "tri_1536": [W.subband(15, 2, 1200, 8, 1536, 3072, c, "sync_ols") for c in (-700, -200, 200, 700)],
 }
 
 

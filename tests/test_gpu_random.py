@@ -119,3 +119,43 @@ def test_random_plan(seed):
     if all(s["mode"].startswith("sync") for s in sbs):
         got, ref = run_rx(sbs, "c64", seed=seed, weights="random", demod=True)
         assert_gate(got, ref, "c64", "random demod RX %d" % seed)
+
+
+def draw_wide(seed):
+    """One valid synchronised plan with wide groups (three to six subbands
+    of 256 to 2048 points sharing one 2048- or 4096-point transform): the
+    demodulating RX's subband regions then take 20 to 64 KB, so in FP16 /
+    BF16 storage its second-block terms go to device scratch (and groups
+    beyond 8192 region entries are split)."""
+    from paper_2008_00672_amd import FcError, Plan
+    rng = np.random.default_rng(seed)
+    while True:
+        mode = ("sync_ola", "sync_ols")[int(rng.integers(0, 2))]
+        N = int(2048 << rng.integers(0, 2))
+        n_sym = int(rng.integers(1, 4))
+        ncp = [int(v) for v in rng.integers(1, N // 8, n_sym)]
+        sbs = []
+        for m in range(int(rng.integers(3, 7))):
+            L = int(min(N // 2, 256 << rng.integers(0, 4)))       # 256 .. 2048
+            n_tb = int(rng.integers(0, 9))
+            K = 2 * int(rng.integers(0, (L - 2 * n_tb) // 2 + 1))
+            cmax = N // 2 - L // 2
+            s = W.subband(30, n_sym, K, n_tb, L, N, int(rng.integers(-cmax, cmax + 1)), mode)
+            s["ncp_high"] = ncp
+            sbs.append(s)
+        try:
+            Plan(sbs, device=-1)
+        except FcError:
+            continue
+        return sbs
+
+
+@pytest.mark.parametrize("io", ["f16", "bf16"])
+@pytest.mark.parametrize("seed", list(range(300, 306)))
+def test_random_demod_half_storage(seed, io):
+    sbs = draw_wide(seed)
+    print("seed %d %s: %s" % (seed, io, ", ".join("%s L%d N%d c%d K%d tb%d B%d" % (
+        s["mode"], s["n_short"], s["n_long"], s["center_bin"], s["n_active"], s["n_tb"], s["n_symbols"])
+        for s in sbs)), flush=True)
+    got, ref = run_rx(sbs, io, seed=seed, weights="random", demod=True)
+    assert_gate(got, ref, io, "random demod RX %d" % seed)

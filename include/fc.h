@@ -26,7 +26,8 @@
  *     I = n_long / n_short is the interpolation factor.
  *   - Every device pointer is owned by the caller and must stay valid until the
  *     work queued on the given stream has completed. The plan owns its own
- *     device tables (descriptors, twiddles, weights).
+ *     device tables (descriptors, twiddles, weights) and scratch (the
+ *     demodulating receiver's and the weight gradient's per-task slots).
  *   - Calls that take a stream are asynchronous on that stream (a hipStream_t
  *     passed as void*; NULL means the default stream) and never synchronise the
  *     host, except where a function says so (weights from host memory,

@@ -246,6 +246,12 @@ def wgrad_cost(sbs):
     return flops
 
 
+def plan_of(tune):
+    """1 when a tuning runs transform plan 1 anywhere (the op's plan or a
+    kernel class chosen by the autotuner), else 0."""
+    return 1 if tune.get("plan", 0) or tune.get("classes_plan1", 0) else 0
+
+
 def traffic(op, run_len, plan=0):
     """HBM bytes per call of op at run_len blocks per task from the committed
     rocprofv3 counter summary (profiles/traffic_<op>.json), or None when the
@@ -815,6 +821,8 @@ def main():
     rx_demod = dict({"ms": round(rxd_ms, 4), "value": round(rx_samples / (rxd_ms * 1e-3) / 1e6, 1),
                      "unit": "Msamples/s", "achieved_tflops": round(rxd_flops / rxd_ms / 1e9, 2),
                      "algorithmic_flops": int(rxd_flops), "kernel": "fc_rxd_kernel<bf16, N=4096>",
+                     "algorithmic_bytes": int(rx_bytes),
+                     "traffic": traffic("fc_rxd", tune["rx_demod"]["run_len"], plan_of(tune["rx_demod"])),
                      "form": "synchronised RX + OFDM demodulation, one short IFFT + one FFT per symbol (Sec. V-A)"},
                     **frac(rxd_flops / rxd_ms / 1e9))
     log("rx demod: %.3f ms (%.1f TFLOP/s)" % (rxd_ms, rx_demod["achieved_tflops"]))
@@ -834,6 +842,7 @@ def main():
     tx_grid = dict({"ms": round(txg_ms, 4), "value": round(tx_samples / (txg_ms * 1e-3) / 1e6, 1),
                     "unit": "Msamples/s", "achieved_tflops": round(txg_flops / txg_ms / 1e9, 2),
                     "algorithmic_flops": int(txg_flops),
+                    "traffic": traffic("fc_tx_grid", tune["tx_grid"]["run_len"], plan_of(tune["tx_grid"])),
                     "form": "QAM grid in (FP16): OFDM IFFT + truncated CP + synchronised FC TX in the kernels "
                             "(the OFDM IFFT is run for each of a symbol's two blocks)"},
                    **frac(txg_flops / txg_ms / 1e9))
@@ -868,7 +877,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
-    roof["traffic"] = traffic(dk, tune["rx"]["run_len"], tune["rx"].get("plan", 0))
+    roof["traffic"] = traffic(dk, tune["rx"]["run_len"], plan_of(tune["rx"]))
     roof["kernel"] = "fc_rx_kernel<bf16, N=4096> (one launch per RX call)"
     roof["algorithmic_bytes"] = int(d_bytes)
     roof["algorithmic_flops"] = int(d_flops)
@@ -883,7 +892,7 @@ def main():
                             "achieved_tflops_nominal": round(tx_flops_nominal / tx_ms / 1e9, 2),
                             "hbm_gbs": round(tx_bytes / tx_ms / 1e6, 1), "algorithmic_bytes": int(tx_bytes),
                             "algorithmic_flops": int(tx_flops),
-                            "traffic": traffic("fc_tx", tune["tx"]["run_len"], tune["tx"].get("plan", 0))},
+                            "traffic": traffic("fc_tx", tune["tx"]["run_len"], plan_of(tune["tx"]))},
                            **frac(tx_tf))
 
     # ---------------- launch overhead of unbatched calls ----------------

@@ -392,7 +392,7 @@ fc_status fc_plan_get_class_plans(const fc_plan* plan, int32_t op, int32_t* n_cl
  * own and spreads the launches over the streams longest first by those
  * measured times (kept until the next fc_plan_set_tuning). Last, class by
  * class (largest first), it keeps the other transform plan for a kernel
- * class where the whole call then times at least 0.5 % faster. Synchronous.
+ * class where the whole call then times at least 1.5 % faster. Synchronous.
  * The chosen values and time per call (ms) are written to the non-NULL
  * result pointers; the chosen transform plans are read back with
  * fc_plan_get_transform_plan and fc_plan_get_class_plans.

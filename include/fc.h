@@ -384,13 +384,15 @@ fc_status fc_plan_get_class_plans(const fc_plan* plan, int32_t op, int32_t* n_cl
  * call; out is overwritten) for run_len in {0, 8, 16, 32, 64} (TX) or
  * {0, 1, 2, 4, 8, 16} (RX, adjoint; {0, 2, 4, 8, 16} demodulating RX) and
  * conc in {1, 4}, and the transform plans 0 and 1 where they differ for
- * this op (fc_plan_set_transform_plan), one warm-up and six timed calls each (HIP events on
- * `stream`, minimum kept; on a stream other than the legacy null stream the
- * call is captured once as a HIP graph and the replays are timed, so host
- * launch gaps do not enter the choice), then applies the
- * fastest. With conc > 1 it first times every kernel launch of the op on its
- * own and spreads the launches over the streams longest first by those
- * measured times (kept until the next fc_plan_set_tuning). Last, class by
+ * this op (fc_plan_set_transform_plan), each by one warm-up call and three
+ * bursts of four calls back to back (HIP events on `stream`, the shortest
+ * burst's time per call kept; on a stream other than the legacy null stream
+ * the call is captured once as a HIP graph and the replays are timed, so
+ * host launch gaps do not enter the choice), then applies the
+ * fastest. With conc > 1 each candidate is timed twice: with the launches
+ * spread over the streams longest first by the planner's work estimate, and
+ * by their measured times (every kernel launch of the op timed on its own);
+ * the better order is kept (until the next fc_plan_set_tuning). Last, class by
  * class (largest first), it keeps the other transform plan for a kernel
  * class where the whole call then times at least 1.5 % faster. Synchronous.
  * The chosen values and time per call (ms) are written to the non-NULL

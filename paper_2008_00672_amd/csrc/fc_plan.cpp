@@ -1185,11 +1185,13 @@ static bool has_second_plan(const fc_plan* P, int op) {
   return false;
 }
 
-// Time of one call of op under the current tuning: the minimum over six
-// calls after a warm-up. On a capturable stream the call is recorded once as
-// a HIP graph and the graph is replayed, so host launch gaps between the op's
-// kernels stay out of the time (they vary between runs by more than the work
-// splits differ); on the legacy null stream the calls run eagerly.
+// Time of one call of op under the current tuning: calls back to back, as a
+// caller streaming work issues them (one warm-up call, then three bursts of
+// four calls between two events; the shortest burst's time per call). On a
+// capturable stream the call is recorded once as a HIP graph and the graph
+// is replayed, so host launch gaps between the op's kernels stay out of the
+// time (they vary between runs by more than the work splits differ); on the
+// legacy null stream the calls run eagerly.
 static fc_status time_op(fc_plan* P, int op, const void* in, void* out, hipStream_t st, hipEvent_t e0,
                          hipEvent_t e1, float* t_min) {
   hipGraph_t g = nullptr;
@@ -1202,15 +1204,19 @@ static fc_status time_op(fc_plan* P, int op, const void* in, void* out, hipStrea
     if (r == FC_OK && !ended) r = FC_E_DEVICE;
     if (r == FC_OK && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) r = FC_E_DEVICE;
   }
+  auto call = [&]() { return ge ? (hipGraphLaunch(ge, st) == hipSuccess ? FC_OK : FC_E_DEVICE)
+                                 : run_op(P, op, in, out, st); };
+  constexpr int kBurst = 4;
   *t_min = 1e30f;
-  for (int rep = 0; rep < 7 && r == FC_OK; ++rep) {       // one warm-up, six timed calls
+  if (r == FC_OK) r = call();                               // warm-up
+  for (int rep = 0; rep < 3 && r == FC_OK; ++rep) {
     if (hipEventRecord(e0, st) != hipSuccess) { r = FC_E_DEVICE; break; }
-    r = ge ? (hipGraphLaunch(ge, st) == hipSuccess ? FC_OK : FC_E_DEVICE) : run_op(P, op, in, out, st);
+    for (int k = 0; k < kBurst && r == FC_OK; ++k) r = call();
     if (r != FC_OK) break;
     if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { r = FC_E_DEVICE; break; }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (rep > 0) *t_min = std::min(*t_min, ms);
+    *t_min = std::min(*t_min, ms / kBurst);
   }
   if (ge) (void)hipGraphExecDestroy(ge);
   if (g) (void)hipGraphDestroy(g);
@@ -1232,6 +1238,7 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) result = FC_E_DEVICE;
   float best = 1e30f;
   int b_len = P->run_len[op], b_conc = P->conc[op], b_tp = P->tplan[op];
+  bool b_meas = false;                     // launches ordered by measured (not estimated) work
   const int n_tp = has_second_plan(P, op) ? 2 : 1;
   const auto saved_classes = P->class_tp[op];
   P->class_tp[op].clear();
@@ -1241,17 +1248,24 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
       for (int len : lens) {
         if (result != FC_OK) break;
         if ((result = fc_plan_set_tuning(P, op, len, conc)) != FC_OK) break;
-        if (conc > 1 && (result = measure_costs(P, op, in, out, st, e0, e1)) != FC_OK) break;
-        float t_min = 1e30f;
-        result = time_op(P, op, in, out, st, e0, e1, &t_min);
-        if (result == FC_OK && t_min < best) { best = t_min; b_len = len; b_conc = conc; b_tp = tp; }
+        // with several streams: the launches spread by the planner's work
+        // estimate, then by each launch's measured time (neither order wins
+        // on every workload)
+        for (int meas = 0; meas < (conc > 1 ? 2 : 1) && result == FC_OK; ++meas) {
+          if (meas && (result = measure_costs(P, op, in, out, st, e0, e1)) != FC_OK) break;
+          float t_min = 1e30f;
+          result = time_op(P, op, in, out, st, e0, e1, &t_min);
+          if (result == FC_OK && t_min < best) {
+            best = t_min; b_len = len; b_conc = conc; b_tp = tp; b_meas = meas != 0;
+          }
+        }
       }
     }
   }
   P->tplan[op] = b_tp;
   if (result != FC_OK) P->class_tp[op] = saved_classes;
   if (result == FC_OK) result = fc_plan_set_tuning(P, op, b_len, b_conc);
-  if (result == FC_OK && b_conc > 1) result = measure_costs(P, op, in, out, st, e0, e1);
+  if (result == FC_OK && b_meas) result = measure_costs(P, op, in, out, st, e0, e1);
   // then, class by class (largest first), the other transform plan where it
   // makes the whole call at least 1.5 % faster (well above the timing noise
   // of the minimum of six replays): the classes share the GPU, so each
@@ -1269,14 +1283,14 @@ fc_status fc_plan_autotune(fc_plan* P, int32_t op, const void* in, void* out, vo
     for (size_t i = 0; i < keys.size() && result == FC_OK; ++i) {
       P->class_tp[op][keys[i]] = 1 - b_tp;
       if ((result = fc_plan_set_tuning(P, op, b_len, b_conc)) != FC_OK) break;
-      if (b_conc > 1 && (result = measure_costs(P, op, in, out, st, e0, e1)) != FC_OK) break;
+      if (b_meas && (result = measure_costs(P, op, in, out, st, e0, e1)) != FC_OK) break;
       float t = 1e30f;
       if ((result = time_op(P, op, in, out, st, e0, e1, &t)) != FC_OK) break;
       if (t < 0.985f * cur) cur = t;
       else P->class_tp[op].erase(keys[i]);
     }
     if (result == FC_OK) result = fc_plan_set_tuning(P, op, b_len, b_conc);
-    if (result == FC_OK && b_conc > 1) result = measure_costs(P, op, in, out, st, e0, e1);
+    if (result == FC_OK && b_meas) result = measure_costs(P, op, in, out, st, e0, e1);
     if (result == FC_OK) best = cur;
   }
   if (e0) (void)hipEventDestroy(e0);

@@ -1,12 +1,13 @@
-"""The host planner under AddressSanitizer (CPU only, no GPU code is
-instrumented): fc_plan.cpp is rebuilt with -fsanitize=address on the host
-side and linked, with the library's other objects as built, into a C++
+"""The host planner under AddressSanitizer and UndefinedBehaviorSanitizer
+(CPU only, no GPU code is instrumented): fc_plan.cpp is rebuilt with
+-fsanitize=address,undefined on the host side and linked, with the library's other objects as built, into a C++
 driver that creates host-only plans (device = -1) for a few hundred seeded
 random configurations (valid and invalid: every mode, power-of-two and
 mixed-radix sizes, sizes the library rejects, one to six subbands on one or
 two streams, explicit CP schedules, tapers) and reads every layout, CP
 schedule and statistic, retunes every operation and destroys the plan. Any
-out-of-bounds access, use after free or leak in the planner fails the run.
+out-of-bounds access, use after free, leak or undefined behaviour (signed
+overflow, bad shift, misaligned access) in the planner fails the run.
 """
 import os
 import shutil
@@ -119,7 +120,8 @@ def test_planner_under_asan(tmp_path):
     objs = sorted(f for f in os.listdir(BUILD) if f.endswith(".o") and "fc_plan" not in f)
     assert len(objs) == len(B.UNITS) - 1, objs
     base = [B.hipcc(), "-O1", "-g", "-std=c++17", "--offload-arch=gfx950", "-fno-omit-frame-pointer",
-            "-Xarch_host", "-fsanitize=address", "-I", os.path.join(ROOT, "include")]
+            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-I", os.path.join(ROOT, "include")]
     plan_o = str(tmp_path / "fc_plan_asan.o")
     drv = tmp_path / "driver.cpp"
     drv.write_text(DRIVER)
@@ -132,4 +134,4 @@ def test_planner_under_asan(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     print(r.stdout[-2000:], r.stderr[-4000:])
     assert r.returncode == 0, r.stderr[-4000:]
-    assert "AddressSanitizer" not in r.stderr and "LeakSanitizer" not in r.stderr
+    assert "Sanitizer" not in r.stderr and "runtime error" not in r.stderr

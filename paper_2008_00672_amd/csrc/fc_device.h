@@ -1159,10 +1159,7 @@ struct LoadPadded : NoPrefetch {
 };
 
 // Last pass of that FFT: x[u] = (C V)[u] + B[u], scaled by 1/sqrt(L), to the
-// symbol's subcarrier u. With B in device scratch (GB) each B load waits for
-// the previous output store (the compiler cannot tell the two buffers
-// apart); fetching them ahead in registers cost the kernel its third wave
-// per SIMD and measured no faster.
+// symbol's subcarrier u (B from the scratch slot or the second region set).
 template <int IO, int NT, int L, int RM, bool GB> struct StoreSubcarriers : NoPrefetch {
   const float2* B; typename Io<IO>::T* out; float scale;
   __device__ __forceinline__ void operator()(int, int u, float2 v, int up) const {
@@ -1170,6 +1167,22 @@ template <int IO, int NT, int L, int RM, bool GB> struct StoreSubcarriers : NoPr
     Io<IO>::st(out, u, make_float2(x.x * scale, x.y * scale));
   }
 };
+
+// The FFT back with its last pass's B loads and subcarrier stores through
+// restrict-qualified pointers: within the call the compiler knows that the
+// scratch B and the output do not overlap, so it issues the B loads ahead
+// of the earlier stores instead of each after the store before it (with B in
+// device scratch: 1.58 -> 1.51 ms on the 100 MHz bank, registers unchanged).
+template <int IO, int NT, int LL, int RM, bool GB>
+__device__ __forceinline__ void rxd_back(float2* R, int t, const float2* __restrict__ B,
+                                         typename Io<IO>::T* __restrict__ out, float scale,
+                                         const float2* tw) {
+  LoadPadded lp;
+  lp.A = R;
+  StoreSubcarriers<IO, NT, LL, RM, GB> so;
+  so.B = B; so.out = out; so.scale = scale;
+  fft_run<NT, LL, 0, -1, RM>(R, t, lp, so, tw);
+}
 
 // Synchronised RX with OFDM demodulation in the simplified joint form of
 // Sec. V-A. Tasks hold whole symbols (block pairs). Per symbol: the second
@@ -1254,12 +1267,7 @@ __global__ __launch_bounds__(kThreads, rxd_waves_per_simd(IO)) void fc_rxd_kerne
           sm.A = R; sm.half = LL / 2; sm.inv_l = 1.f / LL;
           fft_run<64, LL, 0, +1, RMW>(R, lane, lv, sm, tw);
           wave_sync();
-          LoadPadded lp;
-          lp.A = R;
-          StoreSubcarriers<IO, 64, LL, RMW, GB> so;
-          so.B = Bm; so.out = at<IO>(a.out, a.bsb[B1.bs + m].x0);
-          so.scale = rsqrtf((float)LL);
-          fft_run<64, LL, 0, -1, RMW>(R, lane, lp, so, tw);
+          rxd_back<IO, 64, LL, RMW, GB>(R, lane, Bm, at<IO>(a.out, a.bsb[B1.bs + m].x0), rsqrtf((float)LL), tw);
         }
       }
     };
@@ -1282,12 +1290,8 @@ __global__ __launch_bounds__(kThreads, rxd_waves_per_simd(IO)) void fc_rxd_kerne
           __syncthreads();
           fft_run<kThreads, LL, 0, +1, RMG>(R, tid, lv, sm, tw);
           __syncthreads();
-          LoadPadded lp;
-          lp.A = R;
-          StoreSubcarriers<IO, kThreads, LL, RMG, GB> so;
-          so.B = Bm; so.out = at<IO>(a.out, a.bsb[B1.bs + m].x0);
-          so.scale = rsqrtf((float)LL);
-          fft_run<kThreads, LL, 0, -1, RMG>(R, tid, lp, so, tw);
+          rxd_back<IO, kThreads, LL, RMG, GB>(R, tid, Bm, at<IO>(a.out, a.bsb[B1.bs + m].x0), rsqrtf((float)LL),
+                                             tw);
         }
       }
     };
